@@ -1,0 +1,216 @@
+"""FP64 CPU oracle for the SPIIR filter-bank hot path (test infrastructure).
+
+Only the test-suite, the package smoke check and the benchmark's CPU-baseline
+leg use this package.  The HIP library never imports, links or calls it, and it
+never calls the HIP library: the two share nothing but the seeded inputs of
+``synth``.
+
+What it computes (each function cites the passage it follows):
+
+* ``filter``         Eq. zk (Section II.B.1), read as a sum of independent
+                     first-order complex IIR filters, in FP64.
+* ``filter_stream``  the same, in consecutive chunks with state and input
+                     history carried (data arrives in packets, Section II.A).
+* ``peaks``          largest |z| per template per window and its index
+                     (trigger selection, Section II.C.1), FP64.
+* ``peaks_f32``      the same decision taken in float32 on a complex64 series.
+* ``grad``           gradient of a real loss w.r.t. a_k, b_k by forward-mode
+                     sensitivities.
+* ``overlap_grad``   overlap (Eq. overlap) between the summed impulse response
+                     and a target, and its closed-form gradient.
+
+Complex gradients follow the convention dL/dRe + i dL/dIm.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spiir_oracle.c")
+_LIB = os.path.join(_HERE, "libspiir_oracle.so")
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_F64 = ctypes.c_double
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        lib.spo_filter.argtypes = [_I32, _P, _P, _P, _P, _I32, _I64, _P, _I64, _P, _P, _P]
+        lib.spo_peaks.argtypes = [_I64, _I64, _I64, _P, _P, _P, _P]
+        lib.spo_grad.argtypes = [_I32, _P, _P, _P, _P, _I32, _I64, _P, _P, _P, _P]
+        lib.spo_overlap_grad.argtypes = [_I32, _P, _P, _P, _P, _I64, _P, _I32, _F64, _P, _P, _P]
+        for f in (lib.spo_filter, lib.spo_peaks, lib.spo_grad, lib.spo_overlap_grad):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(arr: Optional[np.ndarray]):
+    return None if arr is None else arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def _bank_arrays(bank):
+    """CSR offsets, complex128 a and b (exact promotion), int32 delays."""
+    offsets = np.ascontiguousarray(bank.offsets, dtype=np.int32)
+    a = np.ascontiguousarray(bank.a, dtype=np.complex128)
+    b = np.ascontiguousarray(bank.b, dtype=np.complex128)
+    d = np.ascontiguousarray(bank.d, dtype=np.int32)
+    return offsets, a, b, d
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what}: invalid arguments (status {rc})")
+
+
+def filter(bank, x: np.ndarray, hist: Optional[np.ndarray] = None,
+           state: Optional[np.ndarray] = None) -> np.ndarray:
+    """complex128 z[D][T][n] for real input x[D][n] (Eq. zk, Section II.B.1).
+
+    ``hist`` ([D][H]) holds the H samples just before x (zero before that);
+    ``state`` (complex128 [D][F]) holds y_k before x and is updated in place to
+    y_k at the last sample.  Both default to a stream starting at x.  Inputs
+    are promoted to float64 (exactly, for float32 data).
+    """
+    offsets, a, b, d = _bank_arrays(bank)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+    n_det, n = x.shape
+    hist_len = 0
+    if hist is not None:
+        hist = np.ascontiguousarray(np.atleast_2d(hist), dtype=np.float64)
+        assert hist.shape[0] == n_det
+        hist_len = hist.shape[1]
+    if state is not None:
+        assert state.dtype == np.complex128 and state.flags.c_contiguous
+        assert state.shape == (n_det, bank.n_filters)
+    z = np.empty((n_det, bank.n_templates, n), dtype=np.complex128)
+    rc = _load().spo_filter(bank.n_templates, _ptr(offsets), _ptr(a), _ptr(b), _ptr(d), n_det, n,
+                            _ptr(x), hist_len, _ptr(hist), _ptr(state), _ptr(z))
+    _check(rc, "filter")
+    return z
+
+
+def filter_stream(bank, x: np.ndarray, chunk: int) -> np.ndarray:
+    """``filter`` over x[D][N] in consecutive chunks with carried state/history."""
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+    n_det, n_total = x.shape
+    hist_len = max(bank.max_delay, 1)
+    hist = np.zeros((n_det, hist_len), dtype=np.float64)
+    state = np.zeros((n_det, bank.n_filters), dtype=np.complex128)
+    out = np.empty((n_det, bank.n_templates, n_total), dtype=np.complex128)
+    for lo in range(0, n_total, chunk):
+        hi = min(lo + chunk, n_total)
+        out[:, :, lo:hi] = filter(bank, x[:, lo:hi], hist=hist, state=state)
+        hist = np.concatenate([hist, x[:, lo:hi]], axis=1)[:, -hist_len:].copy()
+    return out
+
+
+def peaks(z: np.ndarray, window: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Per row of z[..., n] and window: (max |z|, argmax in window, top-2 margin), FP64.
+
+    Ties in |z|^2 go to the lowest index.  Margin is (p1 - p2)/p1 over |z|.
+    """
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    lead, n = z.shape[:-1], z.shape[-1]
+    rows = int(np.prod(lead)) if lead else 1
+    n_win = (n + window - 1) // window
+    peak = np.empty(rows * n_win, dtype=np.float64)
+    arg = np.empty(rows * n_win, dtype=np.int32)
+    margin = np.empty(rows * n_win, dtype=np.float64)
+    rc = _load().spo_peaks(rows, n, window, _ptr(z), _ptr(peak), _ptr(arg), _ptr(margin))
+    _check(rc, "peaks")
+    shape = tuple(lead) + (n_win,)
+    return peak.reshape(shape), arg.reshape(shape), margin.reshape(shape)
+
+
+def peaks_f32(z: np.ndarray, window: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Peak decision taken in float32 on a complex64 series.
+
+    |z|^2 = re*re + im*im with each product and the sum rounded to float32 (no
+    fused multiply-add); the largest per window, lowest index on ties; the peak
+    value is the float32 square root of the winning |z|^2.
+    """
+    z = np.ascontiguousarray(z, dtype=np.complex64)
+    lead, n = z.shape[:-1], z.shape[-1]
+    n_win = (n + window - 1) // window
+    re = z.real.astype(np.float32)
+    im = z.imag.astype(np.float32)
+    p = (re * re).astype(np.float32) + (im * im).astype(np.float32)
+    pad = n_win * window - n
+    if pad:
+        p = np.concatenate([p, np.full(tuple(lead) + (pad,), -np.inf, np.float32)], axis=-1)
+    p = p.reshape(tuple(lead) + (n_win, window))
+    arg = np.argmax(p, axis=-1).astype(np.int32)          # first occurrence on ties
+    best = np.take_along_axis(p, arg[..., None].astype(np.int64), axis=-1)[..., 0]
+    return np.sqrt(best).astype(np.float32), arg
+
+
+def grad(bank, x: np.ndarray, gz: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """(grad_a, grad_b) complex128 [F] of a loss with dL/dz = gz[D][T][n].
+
+    The forward pass starts from zero state and zero history.
+    """
+    offsets, a, b, d = _bank_arrays(bank)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+    n_det, n = x.shape
+    gz = np.ascontiguousarray(gz, dtype=np.complex128).reshape(n_det, bank.n_templates, n)
+    ga = np.empty(bank.n_filters, dtype=np.complex128)
+    gb = np.empty(bank.n_filters, dtype=np.complex128)
+    rc = _load().spo_grad(bank.n_templates, _ptr(offsets), _ptr(a), _ptr(b), _ptr(d), n_det, n,
+                          _ptr(x), _ptr(gz), _ptr(ga), _ptr(gb))
+    _check(rc, "grad")
+    return ga, gb
+
+
+def overlap_grad(bank, target: np.ndarray, mode: int = 0, scale: Optional[float] = None):
+    """(overlap[T], grad_a[F], grad_b[F]) for loss = scale * sum_t (1 - O_t).
+
+    ``target`` is complex [T][n]; the impulse response is taken over the same
+    n samples.  ``mode`` 0 uses |<g, u>| (phase-maximised), 1 uses Re<g, u>.
+    ``scale`` defaults to 1/T (the mean over templates).
+    """
+    offsets, a, b, d = _bank_arrays(bank)
+    target = np.ascontiguousarray(target, dtype=np.complex128)
+    n_t, n = target.shape
+    assert n_t == bank.n_templates
+    if scale is None:
+        scale = 1.0 / max(n_t, 1)
+    ov = np.empty(n_t, dtype=np.float64)
+    ga = np.empty(bank.n_filters, dtype=np.complex128)
+    gb = np.empty(bank.n_filters, dtype=np.complex128)
+    rc = _load().spo_overlap_grad(bank.n_templates, _ptr(offsets), _ptr(a), _ptr(b), _ptr(d), n,
+                                  _ptr(target), int(mode), float(scale), _ptr(ov), _ptr(ga),
+                                  _ptr(gb))
+    _check(rc, "overlap_grad")
+    return ov, ga, gb
+
+
+def rel_err(z_test: np.ndarray, z_ref: np.ndarray) -> np.ndarray:
+    """Per-series relative L2 error ||z_test - z_ref|| / ||z_ref|| over the last axis."""
+    zt = np.asarray(z_test, dtype=np.complex128)
+    zr = np.asarray(z_ref, dtype=np.complex128)
+    num = np.sqrt(np.sum(np.abs(zt - zr) ** 2, axis=-1))
+    den = np.sqrt(np.sum(np.abs(zr) ** 2, axis=-1))
+    return num / np.where(den > 0, den, 1.0)
