@@ -1,0 +1,162 @@
+/*
+ * spiir.h - C ABI of the MI355X (gfx950) SPIIR filter-bank library.
+ *
+ * The operation (Chu et al., "The SPIIR online coherent pipeline ...",
+ * Section II.B.1, Eq. zk and the text before it): a template is approximated by
+ * the summed response of first-order complex IIR filters, filter k having
+ * feedback a_k, feedforward b_k and an integer delay d_k.  For whitened real
+ * input x[n] (one stream per detector) the library computes
+ *
+ *     y_k[n] = a_k * y_k[n-1] + b_k * x[n - d_k]        (complex, per filter)
+ *     z_t[n] = sum over the filters k of template t of y_k[n]
+ *
+ * i.e. the complex SNR series of every template, and from it the largest |z_t|
+ * per window and its position (the per-template, per-second candidate of the
+ * trigger selection in Section II.C.1).  Filter state and input history are
+ * carried across calls, so a stream can be fed in packets of any length
+ * (Section II.A: data arrive in one-second packets).  Zero state and zero input
+ * precede the first packet.
+ *
+ * Conventions for every entry point:
+ *  - Complex numbers are interleaved float pairs (re, im), i.e. complex64.
+ *  - "host" pointers are read during the call only; the caller keeps ownership.
+ *    "device" pointers are HIP device memory owned by the caller; the library
+ *    reads or writes them asynchronously on the given stream, so they must stay
+ *    valid until that stream has reached the call.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *    asynchronously; a device fault surfaces as SPIIR_E_HIP from a later call.
+ *  - Argument errors are detected on the host before anything is enqueued; the
+ *    call then returns a non-zero status, changes nothing, and spiir_last_error()
+ *    describes the problem.  No C++ exception crosses this interface.
+ *  - A bank is not re-entrant: use one bank from one host thread and one stream
+ *    at a time.
+ */
+#ifndef SPIIR_H
+#define SPIIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spiir_bank spiir_bank; /* opaque: device coefficients, state, history */
+
+typedef enum {
+    SPIIR_OK = 0,
+    SPIIR_E_INVAL = 1,       /* invalid argument (shape, range, NULL, non-finite) */
+    SPIIR_E_NOMEM = 2,       /* host or device allocation failed */
+    SPIIR_E_HIP = 3,         /* a HIP runtime call failed (including earlier async faults) */
+    SPIIR_E_STATE = 4,       /* call not valid in the bank's current state */
+    SPIIR_E_UNSUPPORTED = 5  /* valid request outside what this build implements */
+} spiir_status;
+
+typedef enum {
+    SPIIR_MODE_FP32_SCAN = 0,  /* plain recurrence, float32 state and arithmetic */
+    SPIIR_MODE_BF16_BLOCK = 1  /* time-blocked form, split-bf16 matrix-core products */
+} spiir_mode;
+
+typedef struct {
+    int32_t n_detectors;      /* D >= 1 independent input streams sharing the bank */
+    int32_t max_chunk;        /* largest packet length n accepted by spiir_filter_chunk */
+    int32_t max_delay;        /* input history kept per detector; 0 = largest d_k.
+                                 Must be >= every d_k and <= 8191 */
+    int32_t peak_window;      /* samples per peak window of spiir_filter_chunk;
+                                 0 = one window per packet */
+    int32_t mode;             /* spiir_mode */
+    int32_t filters_per_lane; /* FP32 scan: filters held per GPU lane, 2, 4 or 8; 0 = 4 */
+    int32_t block_len;        /* block form: time-block length L, 64, 128 or 256; 0 = 128 */
+    double long_pole_abs_a;   /* block form: filters with |a_k| above this carry their
+                                 block-to-block state in FP64; <= 0 = 0.999 */
+} spiir_opts;
+
+/* Fill `opts` with defaults: 1 detector, max_chunk 2048, max_delay 0 (from the bank),
+ * one peak window per packet, FP32 scan, 4 filters per lane, L = 128, 0.999. */
+void spiir_opts_default(spiir_opts *opts);
+
+/*
+ * Create a bank from host arrays (copied; the caller keeps and frees them).
+ *   n_templates  T >= 1
+ *   offsets      host int32[T+1], offsets[0] = 0, non-decreasing; template t owns
+ *                filters offsets[t] .. offsets[t+1]-1 (F = offsets[T] >= 0)
+ *   a, b         host complex64[F]: feedback and feedforward coefficients (the
+ *                filter triplet of Section II.B.1); |a_k| < 1, all finite
+ *   delay        host int32[F]: d_k in [0, max_delay] samples
+ *   opts         may be NULL for defaults
+ *   stream       stream used for the uploads
+ *   out          receives the bank; NULL on failure
+ * Allocates all device memory the bank will use: later calls allocate nothing.
+ * Filter state and history start at zero.
+ */
+spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, const float *a,
+                               const float *b, const int32_t *delay, const spiir_opts *opts,
+                               void *stream, spiir_bank **out);
+
+/* Release the bank's device memory (synchronises the bank's last stream).  NULL is ignored. */
+spiir_status spiir_bank_destroy(spiir_bank *bank);
+
+/* Zero the filter state and the input history of every detector: the next packet
+ * is the start of a new stream. */
+spiir_status spiir_bank_reset(spiir_bank *bank, void *stream);
+
+/* Shape of a bank, for callers sizing their buffers. */
+typedef struct {
+    int32_t n_templates, n_detectors, max_chunk, max_delay, peak_window, mode;
+    int64_t n_filters;
+    int64_t device_bytes;     /* device memory held by the bank */
+    int32_t n_slices;         /* FP32 scan work units (filter groups of one template) */
+    int32_t filters_per_lane;
+    int32_t block_len;
+    int32_t n_long_pole;      /* block form: filters carried in FP64 */
+} spiir_bank_info;
+
+spiir_status spiir_bank_get_info(const spiir_bank *bank, spiir_bank_info *info);
+
+/*
+ * Filter one packet of n samples per detector through the bank (Eq. zk,
+ * Section II.B.1), advancing the stream.
+ *   x       device float32 [D][n] (row stride n)
+ *   n       1 <= n <= max_chunk; if peak_window > 0, n must be a multiple of it
+ *   z       device complex64 [D][T][n], or NULL: the SNR series of every template
+ *   peak    device float32 [D][T][W], or NULL: max |z_t| in each window of the
+ *           packet (W = n / peak_window, or 1)
+ *   argmax  device int32 [D][T][W], or NULL: index in the window of that maximum;
+ *           among equal |z|^2 the lowest index.  |z|^2 is re*re + im*im rounded
+ *           in float32 without fused multiply-add, and peak = sqrtf of it.
+ * peak and argmax must both be given or both be NULL.
+ */
+spiir_status spiir_filter_chunk(spiir_bank *bank, const float *x, int32_t n, float *z,
+                                float *peak, int32_t *argmax, void *stream);
+
+/*
+ * Largest |z| per window of a complex series, and its position (the one-candidate-
+ * per-template-per-window rule of Section II.C.1, trigger selection).
+ *   z       device complex64 [rows][n]
+ *   window  >= 1; the last window of a row may be shorter (ragged)
+ *   peak    device float32 [rows][ceil(n/window)]
+ *   argmax  device int32   [rows][ceil(n/window)], index within the window
+ * Same tie and rounding rules as spiir_filter_chunk.  rows = 0 or n = 0 is a no-op.
+ */
+spiir_status spiir_peaks(const float *z, int64_t rows, int32_t n, int32_t window, float *peak,
+                         int32_t *argmax, void *stream);
+
+/*
+ * Kernel timing (diagnostics for roofline reporting).  While enabled, every
+ * spiir_filter_chunk brackets the launch of the bank's main filtering kernel (the
+ * FP32 scan kernel) with a pair of HIP events on the call's stream, for up to
+ * `capacity` launches (the events are created here, not in later calls).
+ * spiir_bank_kernel_time waits for the last recorded launch and returns the summed
+ * kernel time in milliseconds and the number of timed launches; enabling again
+ * restarts the count.  enable = 0 releases the events.
+ */
+spiir_status spiir_bank_set_timing(spiir_bank *bank, int32_t enable, int32_t capacity);
+spiir_status spiir_bank_kernel_time(spiir_bank *bank, double *total_ms, int64_t *launches);
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char *spiir_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIIR_H */

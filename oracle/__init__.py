@@ -63,6 +63,8 @@ def _load():
         lib.spo_overlap_grad.argtypes = [_I32, _P, _P, _P, _P, _I64, _P, _I32, _F64, _P, _P, _P]
         for f in (lib.spo_filter, lib.spo_peaks, lib.spo_grad, lib.spo_overlap_grad):
             f.restype = ctypes.c_int
+        lib.spo_threads.argtypes = []
+        lib.spo_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -205,6 +207,11 @@ def overlap_grad(bank, target: np.ndarray, mode: int = 0, scale: Optional[float]
                                   _ptr(gb))
     _check(rc, "overlap_grad")
     return ov, ga, gb
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().spo_threads())
 
 
 def rel_err(z_test: np.ndarray, z_ref: np.ndarray) -> np.ndarray:

@@ -28,8 +28,22 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define SPO_OK 0
 #define SPO_EINVAL 1
+
+/* Number of threads the parallel loops below use. */
+int spo_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Filtering: Eq. zk (Section II.B.1) as a sum of parallel first-order       */

@@ -1,0 +1,400 @@
+// C-ABI of libspiir: argument validation, bank layout planning and launches.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct spiir_bank {
+    spiir::Bank bk;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+spiir_status fail(spiir_status st, const std::string &msg) {
+    g_error = msg;
+    return st;
+}
+
+#define SPIIR_HIP(expr)                                                                      \
+    do {                                                                                     \
+        const hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                                \
+            return fail(SPIIR_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+int64_t round16(int64_t bytes) { return (bytes + 15) & ~int64_t(15); }
+
+// Device allocation tracked by the bank (freed in destroy).
+template <typename T>
+spiir_status dev_alloc(spiir::Bank &bk, T **ptr, int64_t count) {
+    *ptr = nullptr;
+    const int64_t bytes = round16(std::max<int64_t>(count, 1) * (int64_t)sizeof(T));
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPIIR_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                       hipGetErrorString(e));
+    }
+    bk.allocations.push_back(p);
+    bk.device_bytes += bytes;
+    *ptr = static_cast<T *>(p);
+    return SPIIR_OK;
+}
+
+void free_all(spiir::Bank &bk) {
+    for (void *p : bk.allocations) (void)hipFree(p);
+    bk.allocations.clear();
+}
+
+void release_events(spiir::Bank &bk) {
+    for (hipEvent_t e : bk.ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : bk.ev_stop) (void)hipEventDestroy(e);
+    bk.ev_start.clear();
+    bk.ev_stop.clear();
+    bk.timed = 0;
+}
+
+template <typename T>
+spiir_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
+    if (src.empty()) return SPIIR_OK;
+    SPIIR_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return SPIIR_OK;
+}
+
+#define SPIIR_TRY(expr)                                                                      \
+    do {                                                                                     \
+        const spiir_status st_ = (expr);                                                     \
+        if (st_ != SPIIR_OK) return st_;                                                     \
+    } while (0)
+
+// Plan the FP32-scan layout.  Each template is split into ceil(F_t / (64*fpl))
+// slices of near-equal size.  Inside a template, filters are ordered by
+// d mod 64 and dealt round-robin to slices and then to slots, so that the 64
+// lanes of a slot read the input window at well-spread LDS banks.
+spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, const float *b,
+                       const int32_t *delay, hipStream_t s) {
+    const int32_t T = bk.n_templates;
+    const int per_slice = spiir::kWave * bk.fpl;
+    std::vector<spiir::Slice> slices;
+    std::vector<int32_t> tmpl_slices(T + 1, 0);
+    std::vector<std::vector<int32_t>> members;   // filter indices per slice, in slot order
+    for (int32_t t = 0; t < T; ++t) {
+        tmpl_slices[t] = (int32_t)slices.size();
+        const int32_t lo = offsets[t], hi = offsets[t + 1];
+        const int32_t f = hi - lo;
+        if (f == 0) continue;
+        std::vector<int32_t> idx(f);
+        std::iota(idx.begin(), idx.end(), lo);
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int32_t p, int32_t q) { return (delay[p] & 63) < (delay[q] & 63); });
+        const int32_t ns = (f + per_slice - 1) / per_slice;
+        std::vector<std::vector<int32_t>> part(ns);
+        for (int32_t i = 0; i < f; ++i) part[i % ns].push_back(idx[i]);
+        for (int32_t p = 0; p < ns; ++p) {
+            spiir::Slice sl{};
+            sl.tmpl = t;
+            sl.n_slots = (int32_t)((part[p].size() + spiir::kWave - 1) / spiir::kWave);
+            slices.push_back(sl);
+            members.push_back(std::move(part[p]));
+        }
+    }
+    tmpl_slices[T] = (int32_t)slices.size();
+    int64_t slot = 0;
+    for (auto &sl : slices) {
+        sl.slot_base = (int32_t)slot;
+        slot += sl.n_slots;
+    }
+    if (slot * spiir::kWave > INT32_MAX)
+        return fail(SPIIR_E_UNSUPPORTED, "bank too large for the FP32 scan layout");
+    bk.n_slices = (int32_t)slices.size();
+    bk.n_slots = slot;
+    const int64_t lanes = slot * spiir::kWave;
+    std::vector<float2> ha(lanes, make_float2(0.f, 0.f)), hb(lanes, make_float2(0.f, 0.f));
+    std::vector<int32_t> hd(lanes, 0), hp(lanes, -1);
+    for (size_t si = 0; si < slices.size(); ++si) {
+        const auto &mem = members[si];
+        const int32_t m = slices[si].n_slots;
+        for (size_t i = 0; i < mem.size(); ++i) {
+            // sorted position i -> slot i % m, lane i / m
+            const int64_t g = (int64_t)(slices[si].slot_base + (int32_t)(i % m)) * spiir::kWave +
+                              (int64_t)(i / m);
+            const int32_t k = mem[i];
+            ha[g] = make_float2(a[2 * (int64_t)k], a[2 * (int64_t)k + 1]);
+            hb[g] = make_float2(b[2 * (int64_t)k], b[2 * (int64_t)k + 1]);
+            hd[g] = delay[k];
+            hp[g] = k;
+        }
+    }
+    SPIIR_TRY(dev_alloc(bk, &bk.d_a, lanes));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_b, lanes));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_delay, lanes));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_perm, lanes));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_slices, std::max<int64_t>(bk.n_slices, 1)));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_tmpl_slices, T + 1));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_state, lanes * bk.n_det));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_hist, std::max<int64_t>((int64_t)bk.hist_len * bk.n_det, 1)));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_partial,
+                        std::max<int64_t>((int64_t)bk.n_det * bk.n_slices * bk.max_chunk, 1)));
+    SPIIR_TRY(upload(bk.d_a, ha, s));
+    SPIIR_TRY(upload(bk.d_b, hb, s));
+    SPIIR_TRY(upload(bk.d_delay, hd, s));
+    SPIIR_TRY(upload(bk.d_perm, hp, s));
+    SPIIR_TRY(upload(bk.d_slices, slices, s));
+    SPIIR_TRY(upload(bk.d_tmpl_slices, tmpl_slices, s));
+    // the host staging vectors die at return: wait for the copies
+    SPIIR_HIP(hipStreamSynchronize(s));
+    return SPIIR_OK;
+}
+
+spiir_status zero_stream_state(spiir::Bank &bk, hipStream_t s) {
+    SPIIR_HIP(spiir::launch_zero(bk.d_state, round16(bk.n_slots * spiir::kWave * bk.n_det *
+                                                     (int64_t)sizeof(float2)), s));
+    if (bk.hist_len > 0)
+        SPIIR_HIP(spiir::launch_zero(bk.d_hist,
+                                     round16((int64_t)bk.hist_len * bk.n_det * (int64_t)sizeof(float)),
+                                     s));
+    return SPIIR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void spiir_opts_default(spiir_opts *opts) {
+    if (opts == nullptr) return;
+    std::memset(opts, 0, sizeof(*opts));
+    opts->n_detectors = 1;
+    opts->max_chunk = 2048;
+    opts->max_delay = 0;
+    opts->peak_window = 0;
+    opts->mode = SPIIR_MODE_FP32_SCAN;
+    opts->filters_per_lane = 4;
+    opts->block_len = 128;
+    opts->long_pole_abs_a = 0.999;
+}
+
+const char *spiir_last_error(void) { return g_error.c_str(); }
+
+spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, const float *a,
+                               const float *b, const int32_t *delay, const spiir_opts *opts_in,
+                               void *stream, spiir_bank **out) {
+    try {
+        if (out == nullptr) return fail(SPIIR_E_INVAL, "out is NULL");
+        *out = nullptr;
+        spiir_opts opts;
+        spiir_opts_default(&opts);
+        if (opts_in != nullptr) opts = *opts_in;
+        if (n_templates < 1) return fail(SPIIR_E_INVAL, "n_templates must be >= 1");
+        if (offsets == nullptr) return fail(SPIIR_E_INVAL, "offsets is NULL");
+        if (offsets[0] != 0) return fail(SPIIR_E_INVAL, "offsets[0] must be 0");
+        for (int32_t t = 0; t < n_templates; ++t)
+            if (offsets[t + 1] < offsets[t])
+                return fail(SPIIR_E_INVAL, "offsets must be non-decreasing (template " +
+                                               std::to_string(t) + ")");
+        const int64_t F = offsets[n_templates];
+        if (F > 0 && (a == nullptr || b == nullptr || delay == nullptr))
+            return fail(SPIIR_E_INVAL, "a, b and delay must be non-NULL when the bank has filters");
+        if (opts.n_detectors < 1) return fail(SPIIR_E_INVAL, "n_detectors must be >= 1");
+        if (opts.max_chunk < 1) return fail(SPIIR_E_INVAL, "max_chunk must be >= 1");
+        if (opts.max_delay < 0 || opts.max_delay > spiir::kMaxDelay)
+            return fail(SPIIR_E_INVAL, "max_delay must be in [0, " +
+                                           std::to_string(spiir::kMaxDelay) + "]");
+        if (opts.peak_window < 0) return fail(SPIIR_E_INVAL, "peak_window must be >= 0");
+        if (opts.mode != SPIIR_MODE_FP32_SCAN && opts.mode != SPIIR_MODE_BF16_BLOCK)
+            return fail(SPIIR_E_INVAL, "unknown mode");
+        if (opts.mode == SPIIR_MODE_BF16_BLOCK)
+            return fail(SPIIR_E_UNSUPPORTED, "the split-bf16 block form is not built yet");
+        int fpl = opts.filters_per_lane == 0 ? 4 : opts.filters_per_lane;
+        if (fpl != 2 && fpl != 4 && fpl != 8)
+            return fail(SPIIR_E_INVAL, "filters_per_lane must be 2, 4 or 8");
+        int32_t dmax = 0;
+        for (int64_t k = 0; k < F; ++k) {
+            const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
+            if (!std::isfinite(ar) || !std::isfinite(ai) || !std::isfinite(br) || !std::isfinite(bi))
+                return fail(SPIIR_E_INVAL, "non-finite coefficient at filter " + std::to_string(k));
+            if (ar * ar + ai * ai >= 1.0)
+                return fail(SPIIR_E_INVAL, "|a| >= 1 at filter " + std::to_string(k));
+            if (delay[k] < 0) return fail(SPIIR_E_INVAL, "negative delay at filter " + std::to_string(k));
+            dmax = std::max(dmax, delay[k]);
+        }
+        const int32_t hist_len = opts.max_delay > 0 ? opts.max_delay : dmax;
+        if (dmax > hist_len)
+            return fail(SPIIR_E_INVAL, "delay " + std::to_string(dmax) + " exceeds max_delay " +
+                                           std::to_string(hist_len));
+        if (hist_len > spiir::kMaxDelay)
+            return fail(SPIIR_E_UNSUPPORTED, "delays above " + std::to_string(spiir::kMaxDelay) +
+                                                 " samples are not supported");
+        if (opts.peak_window > opts.max_chunk)
+            return fail(SPIIR_E_INVAL, "peak_window larger than max_chunk");
+
+        auto *h = new (std::nothrow) spiir_bank;
+        if (h == nullptr) return fail(SPIIR_E_NOMEM, "host allocation failed");
+        spiir::Bank &bk = h->bk;
+        bk.n_templates = n_templates;
+        bk.n_filters = F;
+        bk.n_det = opts.n_detectors;
+        bk.max_chunk = opts.max_chunk;
+        bk.hist_len = hist_len;
+        bk.peak_window = opts.peak_window;
+        bk.mode = opts.mode;
+        bk.fpl = fpl;
+        bk.block_len = opts.block_len == 0 ? 128 : opts.block_len;
+        bk.long_pole = opts.long_pole_abs_a > 0 ? opts.long_pole_abs_a : 0.999;
+        int32_t tile = spiir::kWindowFloats - hist_len - spiir::kSub;
+        tile = std::min(tile, bk.max_chunk);
+        tile = std::max(spiir::kSub, tile / spiir::kSub * spiir::kSub);
+        bk.scan_tile = tile;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        spiir_status st = plan_scan(bk, offsets, a, b, delay, s);
+        if (st == SPIIR_OK) {
+            const hipError_t e = spiir::prepare_scan_fp32(bk);
+            if (e != hipSuccess)
+                st = fail(SPIIR_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+        }
+        if (st == SPIIR_OK) st = zero_stream_state(bk, s);
+        if (st == SPIIR_OK) {
+            const hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = fail(SPIIR_E_HIP, std::string("hipStreamSynchronize: ") +
+                                                            hipGetErrorString(e));
+        }
+        if (st != SPIIR_OK) {
+            free_all(bk);
+            delete h;
+            return st;
+        }
+        bk.last_stream = s;
+        *out = h;
+        return SPIIR_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(SPIIR_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(SPIIR_E_INVAL, e.what());
+    }
+}
+
+spiir_status spiir_bank_destroy(spiir_bank *h) {
+    if (h == nullptr) return SPIIR_OK;
+    spiir_status st = SPIIR_OK;
+    const hipError_t e = hipStreamSynchronize(h->bk.last_stream);
+    if (e != hipSuccess) st = fail(SPIIR_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    release_events(h->bk);
+    free_all(h->bk);
+    delete h;
+    return st;
+}
+
+spiir_status spiir_bank_set_timing(spiir_bank *h, int32_t enable, int32_t capacity) {
+    if (h == nullptr) return fail(SPIIR_E_INVAL, "bank is NULL");
+    spiir::Bank &bk = h->bk;
+    SPIIR_HIP(hipStreamSynchronize(bk.last_stream));
+    release_events(bk);
+    if (!enable) return SPIIR_OK;
+    if (capacity < 1 || capacity > (1 << 20)) return fail(SPIIR_E_INVAL, "capacity must be in [1, 2^20]");
+    bk.ev_start.resize(capacity);
+    bk.ev_stop.resize(capacity);
+    for (int32_t i = 0; i < capacity; ++i) {
+        hipError_t e1 = hipEventCreate(&bk.ev_start[i]);
+        hipError_t e2 = hipEventCreate(&bk.ev_stop[i]);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            bk.ev_start.resize(i);
+            bk.ev_stop.resize(i);
+            release_events(bk);
+            return fail(SPIIR_E_HIP, "hipEventCreate failed");
+        }
+    }
+    return SPIIR_OK;
+}
+
+spiir_status spiir_bank_kernel_time(spiir_bank *h, double *total_ms, int64_t *launches) {
+    if (h == nullptr || total_ms == nullptr || launches == nullptr)
+        return fail(SPIIR_E_INVAL, "bank, total_ms or launches is NULL");
+    spiir::Bank &bk = h->bk;
+    *total_ms = 0.0;
+    *launches = 0;
+    if (bk.ev_start.empty()) return fail(SPIIR_E_STATE, "timing is not enabled");
+    const int64_t n = std::min<int64_t>(bk.timed, (int64_t)bk.ev_start.size());
+    if (n > 0) SPIIR_HIP(hipEventSynchronize(bk.ev_stop[n - 1]));
+    double sum = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        float ms = 0.0f;
+        SPIIR_HIP(hipEventElapsedTime(&ms, bk.ev_start[i], bk.ev_stop[i]));
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = n;
+    return SPIIR_OK;
+}
+
+spiir_status spiir_bank_reset(spiir_bank *h, void *stream) {
+    if (h == nullptr) return fail(SPIIR_E_INVAL, "bank is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    h->bk.last_stream = s;
+    return zero_stream_state(h->bk, s);
+}
+
+spiir_status spiir_bank_get_info(const spiir_bank *h, spiir_bank_info *info) {
+    if (h == nullptr || info == nullptr) return fail(SPIIR_E_INVAL, "bank or info is NULL");
+    const spiir::Bank &bk = h->bk;
+    std::memset(info, 0, sizeof(*info));
+    info->n_templates = bk.n_templates;
+    info->n_detectors = bk.n_det;
+    info->max_chunk = bk.max_chunk;
+    info->max_delay = bk.hist_len;
+    info->peak_window = bk.peak_window;
+    info->mode = bk.mode;
+    info->n_filters = bk.n_filters;
+    info->device_bytes = bk.device_bytes;
+    info->n_slices = bk.n_slices;
+    info->filters_per_lane = bk.fpl;
+    info->block_len = bk.block_len;
+    info->n_long_pole = 0;
+    return SPIIR_OK;
+}
+
+spiir_status spiir_filter_chunk(spiir_bank *h, const float *x, int32_t n, float *z, float *peak,
+                                int32_t *argmax, void *stream) {
+    if (h == nullptr) return fail(SPIIR_E_INVAL, "bank is NULL");
+    spiir::Bank &bk = h->bk;
+    if (n < 0 || n > bk.max_chunk)
+        return fail(SPIIR_E_INVAL, "n must be in [0, max_chunk=" + std::to_string(bk.max_chunk) + "]");
+    if (n == 0) return SPIIR_OK;
+    if (x == nullptr) return fail(SPIIR_E_INVAL, "x is NULL");
+    if ((peak == nullptr) != (argmax == nullptr))
+        return fail(SPIIR_E_INVAL, "peak and argmax must both be given or both be NULL");
+    if (peak != nullptr && bk.peak_window > 0 && n % bk.peak_window != 0)
+        return fail(SPIIR_E_INVAL, "n must be a multiple of peak_window");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bk.last_stream = s;
+    const bool timing = bk.timed < (int64_t)bk.ev_start.size();
+    if (timing) SPIIR_HIP(hipEventRecord(bk.ev_start[bk.timed], s));
+    SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, s));
+    if (timing) {
+        SPIIR_HIP(hipEventRecord(bk.ev_stop[bk.timed], s));
+        ++bk.timed;
+    }
+    SPIIR_HIP(spiir::launch_hist_update(bk, x, n, s));
+    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), peak, argmax, s));
+    return SPIIR_OK;
+}
+
+spiir_status spiir_peaks(const float *z, int64_t rows, int32_t n, int32_t window, float *peak,
+                         int32_t *argmax, void *stream) {
+    if (rows < 0 || n < 0) return fail(SPIIR_E_INVAL, "rows and n must be >= 0");
+    if (window < 1) return fail(SPIIR_E_INVAL, "window must be >= 1");
+    if (rows == 0 || n == 0) return SPIIR_OK;
+    if (z == nullptr || peak == nullptr || argmax == nullptr)
+        return fail(SPIIR_E_INVAL, "z, peak and argmax must be non-NULL");
+    SPIIR_HIP(spiir::launch_peaks(reinterpret_cast<const float2 *>(z), rows, n, window, peak, argmax,
+                                  static_cast<hipStream_t>(stream)));
+    return SPIIR_OK;
+}
+
+}  // extern "C"

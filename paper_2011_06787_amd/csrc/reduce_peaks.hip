@@ -1,0 +1,183 @@
+// Template sum, peak search and input-history update.
+//
+// reduce_peaks: z_t[n] = sum over the slices of template t of the slice partials
+// (Eq. zk's sum over a template's filters, Section II.B.1), optionally written
+// out, and per window the largest |z_t| with its position (one candidate per
+// template per window, Section II.C.1).  |z|^2 is formed as re*re + im*im with
+// every product and the sum rounded to float32 (no contraction) so that the
+// decision is reproducible; among equal |z|^2 the lowest index wins.  The
+// block-wide arg-max reduction uses wave shuffles and one LDS exchange.
+#include <climits>
+
+#include "internal.h"
+
+namespace spiir {
+namespace {
+
+constexpr int kPeakThreads = 256;
+
+struct Best {
+    float p;
+    int32_t i;
+};
+
+__device__ __forceinline__ Best better(Best a, Best b) {
+    // larger |z|^2; on a tie the lower index (indices are unique within a window)
+    return (b.p > a.p || (b.p == a.p && b.i < a.i)) ? b : a;
+}
+
+__device__ __forceinline__ float abs2_rn(float re, float im) {
+    // two rounded products and a rounded sum: never contracted into an fma
+#pragma clang fp contract(off)
+    const float rr = re * re;
+    const float ii = im * im;
+    return rr + ii;
+}
+
+__device__ __forceinline__ Best block_best(Best v, Best *scratch) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        Best o;
+        o.p = __shfl_xor(v.p, off);
+        o.i = __shfl_xor(v.i, off);
+        v = better(v, o);
+    }
+    const int wave = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0) scratch[wave] = v;
+    __syncthreads();
+    Best r = scratch[0];
+    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) r = better(r, scratch[w]);
+    __syncthreads();  // scratch may be reused by the next window
+    return r;
+}
+
+// One block per row (template x detector).  The row's series is the sum of
+// `n_parts` partial series starting at `src` with stride `part_stride`.
+__global__ __launch_bounds__(kPeakThreads) void reduce_peaks_kernel(
+    const float2 *__restrict__ src_all, const int32_t *__restrict__ tmpl_parts, int32_t parts_per_det,
+    int32_t part_stride, int32_t n, int32_t n_rows_per_det, float2 *__restrict__ z,
+    float *__restrict__ peak, int32_t *__restrict__ argmax, int32_t window, int32_t n_win) {
+    __shared__ Best scratch[kPeakThreads / kWave];
+    const int t = blockIdx.x;
+    const int det = blockIdx.y;
+    int p0, np;
+    if (tmpl_parts != nullptr) {
+        p0 = tmpl_parts[t];
+        np = tmpl_parts[t + 1] - p0;
+    } else {  // the rows themselves are the series
+        p0 = t;
+        np = 1;
+    }
+    const float2 *src = src_all + ((int64_t)det * parts_per_det + p0) * part_stride;
+    const int64_t row = (int64_t)det * n_rows_per_det + t;
+    float2 *zr = z != nullptr ? z + row * n : nullptr;
+    for (int w = 0; w < n_win; ++w) {
+        const int lo = w * window;
+        const int hi = min(lo + window, n);
+        Best b{-1.0f, INT_MAX};
+        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            float vr = 0.0f, vi = 0.0f;
+            for (int p = 0; p < np; ++p) {
+                const float2 v = src[(int64_t)p * part_stride + i];
+                vr += v.x;
+                vi += v.y;
+            }
+            if (zr != nullptr) zr[i] = make_float2(vr, vi);
+            const float pw = abs2_rn(vr, vi);
+            if (pw > b.p) {  // i increases per thread: first occurrence kept
+                b.p = pw;
+                b.i = i - lo;
+            }
+        }
+        if (peak != nullptr) {
+            const Best r = block_best(b, scratch);
+            if (threadIdx.x == 0) {
+                peak[row * n_win + w] = sqrtf(r.p);
+                argmax[row * n_win + w] = r.i;
+            }
+        }
+    }
+}
+
+// hist[det][j] <- the last hist_len samples of (old history ++ packet).
+// One block per detector; all reads finish before any write (in-place update).
+constexpr int kHistThreads = 1024;
+constexpr int kHistPerThread = (kMaxDelay + kHistThreads) / kHistThreads;
+
+__global__ __launch_bounds__(kHistThreads) void hist_update_kernel(float *__restrict__ hist,
+                                                                   int32_t hist_len,
+                                                                   const float *__restrict__ x,
+                                                                   int32_t n) {
+    const int det = blockIdx.x;
+    float *h = hist + (int64_t)det * hist_len;
+    const float *xd = x + (int64_t)det * n;
+    float v[kHistPerThread];
+#pragma unroll
+    for (int k = 0; k < kHistPerThread; ++k) {
+        const int j = threadIdx.x + k * kHistThreads;
+        v[k] = 0.0f;
+        if (j < hist_len) {
+            const int pos = n - hist_len + j;  // stream position relative to the packet
+            v[k] = pos >= 0 ? xd[pos] : h[hist_len + pos];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kHistPerThread; ++k) {
+        const int j = threadIdx.x + k * kHistThreads;
+        if (j < hist_len) h[j] = v[k];
+    }
+}
+
+__global__ void zero_kernel(float4 *__restrict__ p, int64_t n4) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+}  // namespace
+
+hipError_t launch_reduce_peaks(const Bank &bk, int32_t n, float2 *z, float *peak, int32_t *argmax,
+                               hipStream_t s) {
+    if (n <= 0 || (z == nullptr && peak == nullptr)) return hipSuccess;
+    const int32_t window = bk.peak_window > 0 ? bk.peak_window : n;
+    const int32_t n_win = (n + window - 1) / window;
+    hipLaunchKernelGGL(reduce_peaks_kernel, dim3(bk.n_templates, bk.n_det), dim3(kPeakThreads), 0,
+                       s, bk.d_partial, bk.d_tmpl_slices, bk.n_slices, bk.max_chunk, n,
+                       bk.n_templates, z, peak, argmax, window, n_win);
+    return hipGetLastError();
+}
+
+hipError_t launch_peaks(const float2 *z, int64_t rows, int32_t n, int32_t window, float *peak,
+                        int32_t *argmax, hipStream_t s) {
+    if (rows <= 0 || n <= 0) return hipSuccess;
+    const int32_t n_win = (n + window - 1) / window;
+    // rows are split over grid.x (<= 2^31-1) and grid.y (detector slot, here 1 row block)
+    const int64_t max_x = 1 << 30;
+    for (int64_t r0 = 0; r0 < rows; r0 += max_x) {
+        const int64_t cnt = rows - r0 < max_x ? rows - r0 : max_x;
+        hipLaunchKernelGGL(reduce_peaks_kernel, dim3((unsigned)cnt, 1), dim3(kPeakThreads), 0, s,
+                           z + r0 * n, nullptr, 0, n, n, (int32_t)cnt, nullptr,
+                           peak + r0 * n_win, argmax + r0 * n_win, window, n_win);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_update(const Bank &bk, const float *x, int32_t n, hipStream_t s) {
+    if (n <= 0 || bk.hist_len == 0) return hipSuccess;
+    hipLaunchKernelGGL(hist_update_kernel, dim3(bk.n_det), dim3(kHistThreads), 0, s, bk.d_hist,
+                       bk.hist_len, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return hipSuccess;
+    // callers pass 16-byte multiples (allocations are rounded up)
+    const int64_t n4 = bytes / 16;
+    const int64_t blocks64 = (n4 + 255) / 256;
+    const unsigned blocks = (unsigned)(blocks64 < 4096 ? (blocks64 > 0 ? blocks64 : 1) : 4096);
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, s, static_cast<float4 *>(ptr), n4);
+    return hipGetLastError();
+}
+
+}  // namespace spiir
