@@ -44,15 +44,34 @@ def parse():
     p.add_argument("--steps", type=int, default=64)
     p.add_argument("--warmup", type=int, default=4)
     p.add_argument("--filters-per-lane", type=int, default=0)
+    p.add_argument("--time-tile", type=int, default=0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-check", action="store_true")
-    p.add_argument("--cpu-templates", type=int, default=128,
+    p.add_argument("--cpu-templates", type=int, default=1024,
                    help="templates in the oracle's timed sample (full 64-s stream)")
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of MIB MiB four times "
+                        "(calibrates the HBM byte counters) and exit")
     return p.parse_args()
+
+
+def copy_probe(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "copies": 4}), flush=True)
 
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the template-sharded multi-GPU path is a design, not an implementation.",
@@ -73,7 +92,8 @@ def main():
     x = torch.from_numpy(x_host).to(dev)
     chunks = [x[:, i * chunk:(i + 1) * chunk].contiguous() for i in range(n_chunks)]
     sb = spiir.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=chunk,
-                                   filters_per_lane=args.filters_per_lane)
+                                   filters_per_lane=args.filters_per_lane,
+                                   time_tile=args.time_tile)
     z = torch.empty((D, T, chunk), dtype=torch.complex64, device=dev)
     peak = torch.empty((D, T, 1), dtype=torch.float32, device=dev)
     amax = torch.empty((D, T, 1), dtype=torch.int32, device=dev)
@@ -126,7 +146,7 @@ def main():
                         "64 s of 2048 Hz white noise in 1-s packets, FP32 scan",
             "templates": T, "filters": F, "detectors": D, "packet_samples": chunk,
             "stream_samples": int(x_host.shape[1]), "filters_per_lane": info.filters_per_lane,
-            "slices": info.n_slices,
+            "slices": info.n_slices, "time_tile": info.time_tile, "scan_waves": info.scan_waves,
         },
         "roofline": {
             "kernel": "scan_fp32_kernel",

@@ -65,13 +65,18 @@ typedef struct {
                                  0 = one window per packet */
     int32_t mode;             /* spiir_mode */
     int32_t filters_per_lane; /* FP32 scan: filters held per GPU lane, 2, 4 or 8; 0 = 4 */
+    int32_t time_tile;        /* FP32 scan schedule.  -1 or 0: one wave per filter group
+                                 walks the whole packet.  16..4096 (multiple of 16): the
+                                 persistent work-queue scan with packets cut into time
+                                 tiles of this many samples */
     int32_t block_len;        /* block form: time-block length L, 64, 128 or 256; 0 = 128 */
     double long_pole_abs_a;   /* block form: filters with |a_k| above this carry their
                                  block-to-block state in FP64; <= 0 = 0.999 */
 } spiir_opts;
 
 /* Fill `opts` with defaults: 1 detector, max_chunk 2048, max_delay 0 (from the bank),
- * one peak window per packet, FP32 scan, 4 filters per lane, L = 128, 0.999. */
+ * one peak window per packet, FP32 scan, 4 filters per lane, no time split, L = 128,
+ * 0.999. */
 void spiir_opts_default(spiir_opts *opts);
 
 /*
@@ -106,10 +111,15 @@ typedef struct {
     int64_t device_bytes;     /* device memory held by the bank */
     int32_t n_slices;         /* FP32 scan work units (filter groups of one template) */
     int32_t filters_per_lane;
+    int32_t time_tile;        /* 0 when the scan is not time-split */
+    int32_t scan_waves;       /* grid of the persistent scan */
     int32_t block_len;
     int32_t n_long_pole;      /* block form: filters carried in FP64 */
+    int32_t scan_wait_timeouts; /* persistent-scan dependency waits that hit their bound
+                                   (results of those packets are invalid); 0 normally */
 } spiir_bank_info;
 
+/* Fill `info`.  Waits for the bank's last stream (to read the wait-timeout count). */
 spiir_status spiir_bank_get_info(const spiir_bank *bank, spiir_bank_info *info);
 
 /*

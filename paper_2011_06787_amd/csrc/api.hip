@@ -75,17 +75,19 @@ spiir_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
         if (st_ != SPIIR_OK) return st_;                                                     \
     } while (0)
 
-// Plan the FP32-scan layout.  Each template is split into ceil(F_t / (64*fpl))
-// slices of near-equal size.  Inside a template, filters are ordered by
-// d mod 64 and dealt round-robin to slices and then to slots, so that the 64
-// lanes of a slot read the input window at well-spread LDS banks.
+// Plan the FP32-scan layout.  A template of F_t filters takes the minimum
+// ceil(F_t/64) slots of 64 lanes; these are split into ceil(slots/fpl) slices of
+// near-equal slot counts (<= fpl each).  Inside a template, filters are ordered by
+// d mod 64 and dealt to the slices in that order (each next filter to the slice
+// with the lowest fill ratio), then within a slice the sorted position i goes to
+// slot i % m, lane i / m: the 64 lanes of a slot then read the input window at
+// well-spread LDS banks.
 spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, const float *b,
                        const int32_t *delay, hipStream_t s) {
     const int32_t T = bk.n_templates;
-    const int per_slice = spiir::kWave * bk.fpl;
     std::vector<spiir::Slice> slices;
     std::vector<int32_t> tmpl_slices(T + 1, 0);
-    std::vector<std::vector<int32_t>> members;   // filter indices per slice, in slot order
+    std::vector<std::vector<int32_t>> members;   // filter indices per slice, in sorted order
     for (int32_t t = 0; t < T; ++t) {
         tmpl_slices[t] = (int32_t)slices.size();
         const int32_t lo = offsets[t], hi = offsets[t + 1];
@@ -95,9 +97,24 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
         std::iota(idx.begin(), idx.end(), lo);
         std::stable_sort(idx.begin(), idx.end(),
                          [&](int32_t p, int32_t q) { return (delay[p] & 63) < (delay[q] & 63); });
-        const int32_t ns = (f + per_slice - 1) / per_slice;
+        const int32_t slots = (f + spiir::kWave - 1) / spiir::kWave;
+        const int32_t ns = (slots + bk.fpl - 1) / bk.fpl;
+        std::vector<int32_t> cap(ns);
+        for (int32_t p = 0; p < ns; ++p) cap[p] = (slots / ns + (p < slots % ns ? 1 : 0)) * spiir::kWave;
         std::vector<std::vector<int32_t>> part(ns);
-        for (int32_t i = 0; i < f; ++i) part[i % ns].push_back(idx[i]);
+        for (int32_t i = 0; i < f; ++i) {
+            int32_t best = -1;
+            double best_fill = 2.0;
+            for (int32_t p = 0; p < ns; ++p) {
+                if ((int32_t)part[p].size() >= cap[p]) continue;
+                const double fill = (double)part[p].size() / cap[p];
+                if (fill < best_fill) {
+                    best_fill = fill;
+                    best = p;
+                }
+            }
+            part[best].push_back(idx[i]);
+        }
         for (int32_t p = 0; p < ns; ++p) {
             spiir::Slice sl{};
             sl.tmpl = t;
@@ -143,6 +160,17 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
     SPIIR_TRY(dev_alloc(bk, &bk.d_hist, std::max<int64_t>((int64_t)bk.hist_len * bk.n_det, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_partial,
                         std::max<int64_t>((int64_t)bk.n_det * bk.n_slices * bk.max_chunk, 1)));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_queue, 1));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_flags, std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 4)));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_order, std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 1)));
+    // persistent-scan hand-out order inside a time tile: largest slices first
+    std::vector<int32_t> order((size_t)bk.n_det * bk.n_slices);
+    for (int32_t dd = 0; dd < bk.n_det; ++dd)
+        for (int32_t si = 0; si < bk.n_slices; ++si) order[(size_t)dd * bk.n_slices + si] = dd * bk.n_slices + si;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) {
+        return slices[p % bk.n_slices].n_slots > slices[q % bk.n_slices].n_slots;
+    });
+    SPIIR_TRY(upload(bk.d_order, order, s));
     SPIIR_TRY(upload(bk.d_a, ha, s));
     SPIIR_TRY(upload(bk.d_b, hb, s));
     SPIIR_TRY(upload(bk.d_delay, hd, s));
@@ -164,6 +192,15 @@ spiir_status zero_stream_state(spiir::Bank &bk, hipStream_t s) {
     return SPIIR_OK;
 }
 
+// Work-queue counters and per-slice progress flags of the persistent scan.
+spiir_status zero_queue(spiir::Bank &bk, hipStream_t s) {
+    SPIIR_HIP(spiir::launch_zero(bk.d_queue, round16(sizeof(spiir::ScanQueue)), s));
+    SPIIR_HIP(spiir::launch_zero(bk.d_flags,
+                                 round16(std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 4) *
+                                         (int64_t)sizeof(uint32_t)), s));
+    return SPIIR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -177,6 +214,7 @@ void spiir_opts_default(spiir_opts *opts) {
     opts->peak_window = 0;
     opts->mode = SPIIR_MODE_FP32_SCAN;
     opts->filters_per_lane = 4;
+    opts->time_tile = 0;
     opts->block_len = 128;
     opts->long_pole_abs_a = 0.999;
 }
@@ -215,6 +253,10 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         int fpl = opts.filters_per_lane == 0 ? 4 : opts.filters_per_lane;
         if (fpl != 2 && fpl != 4 && fpl != 8)
             return fail(SPIIR_E_INVAL, "filters_per_lane must be 2, 4 or 8");
+        const int time_tile = opts.time_tile;
+        if (time_tile != -1 && time_tile != 0 &&
+            (time_tile < spiir::kSub || time_tile > 4096 || time_tile % spiir::kSub != 0))
+            return fail(SPIIR_E_INVAL, "time_tile must be -1, 0 or a multiple of 16 in [16, 4096]");
         int32_t dmax = 0;
         for (int64_t k = 0; k < F; ++k) {
             const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
@@ -246,6 +288,7 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         bk.peak_window = opts.peak_window;
         bk.mode = opts.mode;
         bk.fpl = fpl;
+        bk.time_tile = time_tile > 0 ? time_tile : 0;
         bk.block_len = opts.block_len == 0 ? 128 : opts.block_len;
         bk.long_pole = opts.long_pole_abs_a > 0 ? opts.long_pole_abs_a : 0.999;
         int32_t tile = spiir::kWindowFloats - hist_len - spiir::kSub;
@@ -260,6 +303,7 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
                 st = fail(SPIIR_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
         }
         if (st == SPIIR_OK) st = zero_stream_state(bk, s);
+        if (st == SPIIR_OK) st = zero_queue(bk, s);
         if (st == SPIIR_OK) {
             const hipError_t e = hipStreamSynchronize(s);
             if (e != hipSuccess) st = fail(SPIIR_E_HIP, std::string("hipStreamSynchronize: ") +
@@ -354,8 +398,16 @@ spiir_status spiir_bank_get_info(const spiir_bank *h, spiir_bank_info *info) {
     info->device_bytes = bk.device_bytes;
     info->n_slices = bk.n_slices;
     info->filters_per_lane = bk.fpl;
+    info->time_tile = bk.time_tile;
+    info->scan_waves = bk.scan_waves;
     info->block_len = bk.block_len;
     info->n_long_pole = 0;
+    if (bk.d_queue != nullptr) {
+        spiir::ScanQueue q{};
+        SPIIR_HIP(hipStreamSynchronize(bk.last_stream));
+        SPIIR_HIP(hipMemcpy(&q, bk.d_queue, sizeof(q), hipMemcpyDeviceToHost));
+        info->scan_wait_timeouts = (int32_t)q.error;
+    }
     return SPIIR_OK;
 }
 

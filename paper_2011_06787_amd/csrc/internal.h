@@ -17,6 +17,14 @@ constexpr int kScanWaves = 4;      // waves per workgroup of the FP32 scan
 constexpr int kMaxDelay = 8191;    // largest supported delay (samples)
 constexpr int kWindowFloats = 12288;  // LDS input window of the FP32 scan (floats)
 
+// Device bookkeeping of the persistent FP32 scan (one per bank).
+struct ScanQueue {
+    uint32_t head;   // next work item to hand out in the current launch
+    uint32_t done;   // waves of the current launch that have finished
+    uint32_t epoch;  // time tiles every slice completed before the current launch
+    uint32_t error;  // sticky count of dependency waits that hit their bound
+};
+
 // One FP32-scan work unit: up to 64 * filters_per_lane filters of one template.
 // Its filters occupy `n_slots` consecutive slots of 64 lanes starting at `slot_base`.
 struct Slice {
@@ -38,7 +46,9 @@ struct Bank {
     int32_t fpl = 4;           // filters per lane (FP32 scan)
     int32_t block_len = 128;
     double long_pole = 0.999;
-    int32_t scan_tile = 2048;  // samples per LDS input window of the FP32 scan
+    int32_t scan_tile = 2048;  // samples per LDS input window of the one-shot FP32 scan
+    int32_t time_tile = 256;   // samples per work item of the persistent scan; 0 = one-shot
+    int32_t scan_waves = 0;    // resident waves of the persistent scan (grid size)
 
     // FP32 scan layout
     int32_t n_slices = 0;
@@ -52,6 +62,9 @@ struct Bank {
     float2 *d_state = nullptr;   // [D][n_slots*64]
     float *d_hist = nullptr;     // [D][hist_len]
     float2 *d_partial = nullptr; // [D][n_slices][max_chunk]
+    ScanQueue *d_queue = nullptr;
+    uint32_t *d_flags = nullptr; // [D][n_slices]: tiles completed (epoch-relative)
+    int32_t *d_order = nullptr;  // [D*n_slices]: det*n_slices + slice, largest slices first
 
     int64_t device_bytes = 0;
     hipStream_t last_stream = nullptr;
@@ -64,7 +77,8 @@ struct Bank {
 
 // Launchers (enqueue only; arguments already validated).
 size_t scan_fp32_lds_bytes(int32_t tile, int32_t hist_len);
-hipError_t prepare_scan_fp32(const Bank &bk);
+size_t scan_persistent_lds_bytes(int32_t tile, int32_t hist_len);
+hipError_t prepare_scan_fp32(Bank &bk);
 hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, hipStream_t s);
 hipError_t launch_hist_update(const Bank &bk, const float *x, int32_t n, hipStream_t s);
 hipError_t launch_reduce_peaks(const Bank &bk, int32_t n, float2 *z, float *peak,

@@ -16,6 +16,8 @@
 //
 // Arithmetic per filter-sample: 2 mul + 4 fma (complex a*y + b*x with real x)
 // and 2 adds into the lane sum: 8 VALU lane-operations for the paper's 12 flops.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace spiir {
@@ -27,6 +29,33 @@ static_assert(kSub == 16, "the lane reduction assumes 4 quarters of 16 lanes");
 __device__ __forceinline__ void lds_fence() {
     // orders this wave's LDS writes before its later LDS reads (and vice versa)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// Copy the input window x[n0 - hist_len, n0 + T) of one detector into LDS:
+// positions before the packet come from the history ring.  Loads are issued in
+// batches of kBatch per thread before their LDS stores, so that many global loads
+// are in flight at once instead of one latency per element.
+constexpr int kBatch = 16;
+
+__device__ __forceinline__ void load_window(float *__restrict__ win, const float *__restrict__ xd,
+                                            const float *__restrict__ hd, int hist_len, int n0,
+                                            int T, int tid, int nthreads) {
+    const int total = T + hist_len;
+    for (int b0 = 0; b0 < total; b0 += kBatch * nthreads) {
+        float v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = b0 + k * nthreads + tid;
+            const int pos = n0 - hist_len + i;
+            v[k] = 0.0f;
+            if (i < total) v[k] = pos >= 0 ? xd[pos] : hd[hist_len + pos];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int i = b0 + k * nthreads + tid;
+            if (i < total) win[i] = v[k];
+        }
+    }
 }
 
 template <int MAXM, bool TAIL>
@@ -125,10 +154,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     for (int n0 = 0; n0 < n; n0 += tile_len) {
         const int T = min(tile_len, n - n0);
         __syncthreads();  // every wave is done with the previous window
-        for (int i = threadIdx.x; i < T + hist_len; i += blockDim.x) {
-            const int pos = n0 - hist_len + i;
-            win[i] = pos >= 0 ? xd[pos] : hd[hist_len + pos];
-        }
+        load_window(win, xd, hd, hist_len, n0, T, threadIdx.x, blockDim.x);
         __syncthreads();
         if (!active) continue;
         int s0 = 0;
@@ -146,6 +172,156 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     }
 }
 
+// Persistent variant.  The packet is cut into time tiles of `tile` samples and
+// the work items are (detector, slice, tile), handed out in tile-major order
+// (largest slices first inside a tile) by an atomic counter, one item per wave at
+// a time, so every SIMD gets an equal share however uneven the slices are.  An
+// item needs the state its slice reached at the end of the previous tile, which
+// another wave, possibly on another XCD, produced.  The hand-off avoids cache-wide
+// operations: the carried state is written and read with device-scope atomic
+// accesses (coherent across XCDs, not kept in the non-coherent caches); the
+// producer waits for those stores to complete before it advances the slice's flag
+// (a device-scope atomic), and the consumer spins on the flag before it loads the
+// state.  Items are handed out in order, so the producer of any awaited item is
+// already running and the wait ends; it is bounded all the same, and a wait that
+// hits the bound is counted in ScanQueue::error.  Flags count tiles since the bank
+// was created: a launch knows the count every slice reached before it (`epoch`),
+// and the last wave to finish advances the epoch and rewinds the counters for the
+// next launch (kernel boundaries order these with the next launch).
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ float2 load_coherent(const float2 *p) {
+    const uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float2, v);
+}
+
+__device__ __forceinline__ void store_coherent(float2 *p, float2 v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(p), __builtin_bit_cast(uint64_t, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void wait_memory() {
+    // every memory operation this wave issued so far has completed (s_waitcnt with all
+    // counters at zero); no cache maintenance.  The fences keep the compiler from
+    // moving memory accesses across the wait.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
+    const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
+    float2 *__restrict__ state, const Slice *__restrict__ slices, const int32_t *__restrict__ order,
+    int32_t n_slices, int32_t n_det, int64_t lanes_total, const float *__restrict__ x, int32_t n,
+    const float *__restrict__ hist, int32_t hist_len, float2 *__restrict__ partial,
+    int32_t part_stride, int32_t tile, int32_t win_floats, ScanQueue *__restrict__ queue,
+    uint32_t *__restrict__ flags) {
+    extern __shared__ float smem[];
+    float *win = smem;
+    float2 *red = reinterpret_cast<float2 *>(smem + win_floats);
+    const int lane = threadIdx.x;
+    const uint32_t per_round = (uint32_t)n_det * (uint32_t)n_slices;
+    const uint32_t n_tiles = (uint32_t)((n + tile - 1) / tile);
+    const uint32_t total = n_tiles * per_round;
+    const uint32_t epoch = __hip_atomic_load(&queue->epoch, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0)
+            item = __hip_atomic_fetch_add(&queue->head, 1u, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        item = __shfl(item, 0);
+        if (item >= total) break;
+        const uint32_t tau = item / per_round;
+        const int code = order[item % per_round];
+        const int det = code / n_slices;
+        const int sidx = code % n_slices;
+        const Slice sl = slices[sidx];
+        const int m = sl.n_slots;
+        const int n0 = (int)tau * tile;
+        const int T = min(tile, n - n0);
+
+        // input window of this tile: history ring followed by the packet
+        const float *xd = x + (int64_t)det * n;
+        const float *hd = hist + (int64_t)det * hist_len;
+        load_window(win, xd, hd, hist_len, n0, T, lane, kWave);
+
+        float ar[MAXM], ai[MAXM], br[MAXM], bi[MAXM], yr[MAXM], yi[MAXM];
+        int base[MAXM];
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+            if (j < m) {
+                const int64_t g = (int64_t)(sl.slot_base + j) * kWave + lane;
+                const float2 a = ca[g], b = cb[g];
+                ar[j] = a.x; ai[j] = a.y; br[j] = b.x; bi[j] = b.y;
+                base[j] = hist_len - cd[g];
+            } else {
+                ar[j] = ai[j] = br[j] = bi[j] = 0.0f;
+                base[j] = 0;
+            }
+        }
+
+        // wait until the previous tile of this (detector, slice) has published its state
+        uint32_t *flag = flags + (int64_t)det * n_slices + sidx;
+        const uint32_t target = epoch + tau;
+        if (lane == 0) {
+            uint32_t spins = 0;
+            while ((int32_t)(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                             target) < 0) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins == kSpinLimit) {
+                    __hip_atomic_fetch_add(&queue->error, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        wait_memory();
+        float2 *st = state + (int64_t)det * lanes_total;
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+            if (j < m) {
+                const float2 y = load_coherent(st + (int64_t)(sl.slot_base + j) * kWave + lane);
+                yr[j] = y.x; yi[j] = y.y;
+            } else {
+                yr[j] = yi[j] = 0.0f;
+            }
+        }
+        lds_fence();  // window stores visible to every lane of the wave
+        float2 *pout = partial + ((int64_t)det * n_slices + sidx) * part_stride + n0;
+        int s0 = 0;
+        for (; s0 + kSub <= T; s0 += kSub)
+            sub_tile<MAXM, false>(win, red, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
+                                  pout + s0);
+        if (s0 < T)
+            sub_tile<MAXM, true>(win, red, lane, m, s0, T - s0, ar, ai, br, bi, base, yr, yi,
+                                 pout + s0);
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j)
+            if (j < m)
+                store_coherent(st + (int64_t)(sl.slot_base + j) * kWave + lane,
+                               make_float2(yr[j], yi[j]));
+        // publish: the state stores have completed before the flag moves
+        wait_memory();
+        if (lane == 0)
+            __hip_atomic_store(flag, target + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        lds_fence();  // every lane done with the window before the next item overwrites it
+    }
+    // the last wave to finish prepares the bookkeeping for the next launch
+    if (lane == 0) {
+        const uint32_t old = __hip_atomic_fetch_add(&queue->done, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gridDim.x - 1) {
+            __hip_atomic_store(&queue->head, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&queue->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&queue->epoch, epoch + n_tiles, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 }  // namespace
 
 size_t scan_fp32_lds_bytes(int32_t tile, int32_t hist_len) {
@@ -154,48 +330,77 @@ size_t scan_fp32_lds_bytes(int32_t tile, int32_t hist_len) {
            (size_t)kScanWaves * kWave * kRedStride * sizeof(float2);
 }
 
-hipError_t prepare_scan_fp32(const Bank &bk) {
-    // allow the dynamic LDS this bank's window needs (above the 64 KiB default)
-    const int lds = (int)scan_fp32_lds_bytes(bk.scan_tile, bk.hist_len);
-    hipError_t e = hipSuccess;
-    switch (bk.fpl) {
-    case 2: e = hipFuncSetAttribute((const void *)scan_fp32_kernel<2>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
-    case 4: e = hipFuncSetAttribute((const void *)scan_fp32_kernel<4>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
-    case 8: e = hipFuncSetAttribute((const void *)scan_fp32_kernel<8>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
-    default: e = hipErrorInvalidValue;
+size_t scan_persistent_lds_bytes(int32_t tile, int32_t hist_len) {
+    const int32_t win_floats = ((tile + hist_len + kSub) + 3) & ~3;
+    return (size_t)win_floats * sizeof(float) + (size_t)kWave * kRedStride * sizeof(float2);
+}
+
+namespace {
+
+template <int MAXM>
+hipError_t prepare_fpl(Bank &bk) {
+    hipError_t e = hipFuncSetAttribute((const void *)scan_fp32_kernel<MAXM>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)scan_fp32_lds_bytes(bk.scan_tile, bk.hist_len));
+    if (e != hipSuccess || bk.time_tile <= 0) return e;
+    const int lds = (int)scan_persistent_lds_bytes(bk.time_tile, bk.hist_len);
+    e = hipFuncSetAttribute((const void *)scan_fp32_persistent_kernel<MAXM>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, (const void *)scan_fp32_persistent_kernel<MAXM>, kWave, lds);
+    if (e != hipSuccess) return e;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    bk.scan_waves = std::max(1, per_cu) * std::max(1, cus);
+    return hipSuccess;
+}
+
+template <int MAXM>
+void launch_fpl(const Bank &bk, const float *x, int32_t n, hipStream_t s) {
+    const int64_t lanes = bk.n_slots * kWave;
+    if (bk.time_tile > 0) {
+        const int32_t win_floats = ((bk.time_tile + bk.hist_len + kSub) + 3) & ~3;
+        const int64_t items = (int64_t)((n + bk.time_tile - 1) / bk.time_tile) * bk.n_det *
+                              bk.n_slices;
+        const int grid = (int)std::min<int64_t>(bk.scan_waves, items);
+        hipLaunchKernelGGL(scan_fp32_persistent_kernel<MAXM>, dim3(grid), dim3(kWave),
+                           scan_persistent_lds_bytes(bk.time_tile, bk.hist_len), s, bk.d_a, bk.d_b,
+                           bk.d_delay, bk.d_state, bk.d_slices, bk.d_order, bk.n_slices, bk.n_det,
+                           lanes, x, n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk,
+                           bk.time_tile, win_floats, bk.d_queue, bk.d_flags);
+    } else {
+        const int32_t tile = bk.scan_tile;
+        const int32_t win_floats = ((tile + bk.hist_len + kSub) + 3) & ~3;
+        const dim3 grid((bk.n_slices + kScanWaves - 1) / kScanWaves, bk.n_det);
+        hipLaunchKernelGGL(scan_fp32_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
+                           scan_fp32_lds_bytes(tile, bk.hist_len), s, bk.d_a, bk.d_b, bk.d_delay,
+                           bk.d_state, bk.d_slices, bk.n_slices, lanes, x, n, bk.d_hist,
+                           bk.hist_len, bk.d_partial, bk.max_chunk, tile, win_floats);
     }
-    return e;
+}
+
+}  // namespace
+
+hipError_t prepare_scan_fp32(Bank &bk) {
+    switch (bk.fpl) {
+    case 2: return prepare_fpl<2>(bk);
+    case 4: return prepare_fpl<4>(bk);
+    case 8: return prepare_fpl<8>(bk);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, hipStream_t s) {
     if (n <= 0 || bk.n_slices == 0) return hipSuccess;
-    const int32_t tile = bk.scan_tile;
-    const int32_t win_floats = ((tile + bk.hist_len + kSub) + 3) & ~3;
-    const size_t lds = scan_fp32_lds_bytes(tile, bk.hist_len);
-    const dim3 grid((bk.n_slices + kScanWaves - 1) / kScanWaves, bk.n_det);
-    const dim3 block(kWave * kScanWaves);
-    const int64_t lanes = bk.n_slots * kWave;
     switch (bk.fpl) {
-    case 2:
-        hipLaunchKernelGGL(scan_fp32_kernel<2>, grid, block, lds, s, bk.d_a, bk.d_b, bk.d_delay,
-                           bk.d_state, bk.d_slices, bk.n_slices, lanes, x, n, bk.d_hist,
-                           bk.hist_len, bk.d_partial, bk.max_chunk, tile, win_floats);
-        break;
-    case 4:
-        hipLaunchKernelGGL(scan_fp32_kernel<4>, grid, block, lds, s, bk.d_a, bk.d_b, bk.d_delay,
-                           bk.d_state, bk.d_slices, bk.n_slices, lanes, x, n, bk.d_hist,
-                           bk.hist_len, bk.d_partial, bk.max_chunk, tile, win_floats);
-        break;
-    case 8:
-        hipLaunchKernelGGL(scan_fp32_kernel<8>, grid, block, lds, s, bk.d_a, bk.d_b, bk.d_delay,
-                           bk.d_state, bk.d_slices, bk.n_slices, lanes, x, n, bk.d_hist,
-                           bk.hist_len, bk.d_partial, bk.max_chunk, tile, win_floats);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    case 2: launch_fpl<2>(bk, x, n, s); break;
+    case 4: launch_fpl<4>(bk, x, n, s); break;
+    case 8: launch_fpl<8>(bk, x, n, s); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

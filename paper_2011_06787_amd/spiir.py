@@ -47,6 +47,7 @@ class Opts(ctypes.Structure):
         ("peak_window", ctypes.c_int32),
         ("mode", ctypes.c_int32),
         ("filters_per_lane", ctypes.c_int32),
+        ("time_tile", ctypes.c_int32),
         ("block_len", ctypes.c_int32),
         ("long_pole_abs_a", ctypes.c_double),
     ]
@@ -59,7 +60,9 @@ class BankInfo(ctypes.Structure):
         ("peak_window", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("n_filters", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
         ("n_slices", ctypes.c_int32), ("filters_per_lane", ctypes.c_int32),
+        ("time_tile", ctypes.c_int32), ("scan_waves", ctypes.c_int32),
         ("block_len", ctypes.c_int32), ("n_long_pole", ctypes.c_int32),
+        ("scan_wait_timeouts", ctypes.c_int32),
     ]
 
 
@@ -132,8 +135,8 @@ class SpiirBank:
 
     def __init__(self, offsets, a, b, delay, *, n_detectors: int = 1, max_chunk: int = 2048,
                  max_delay: int = 0, peak_window: int = 0, mode: int = MODE_FP32_SCAN,
-                 filters_per_lane: int = 0, block_len: int = 0, long_pole_abs_a: float = 0.999,
-                 stream=None):
+                 filters_per_lane: int = 0, time_tile: int = 0, block_len: int = 0,
+                 long_pole_abs_a: float = 0.999, stream=None):
         lib = load()
         self._offsets = np.ascontiguousarray(offsets, dtype=np.int32)
         self._a = np.ascontiguousarray(a, dtype=np.complex64)
@@ -142,7 +145,7 @@ class SpiirBank:
         o = default_opts()
         o.n_detectors, o.max_chunk, o.max_delay = n_detectors, max_chunk, max_delay
         o.peak_window, o.mode, o.filters_per_lane = peak_window, mode, filters_per_lane
-        o.block_len, o.long_pole_abs_a = block_len, long_pole_abs_a
+        o.time_tile, o.block_len, o.long_pole_abs_a = time_tile, block_len, long_pole_abs_a
         self.opts = o
         h = _P()
         st = lib.spiir_bank_create(int(self._offsets.shape[0] - 1),
@@ -157,6 +160,10 @@ class SpiirBank:
     def from_bank(cls, bank, **kw) -> "SpiirBank":
         """From a ``synth.Bank``-like object with offsets, a, b, d."""
         return cls(bank.offsets, bank.a, bank.b, bank.d, **kw)
+
+    def refresh_info(self) -> BankInfo:
+        self.info = self._info()
+        return self.info
 
     def _info(self) -> BankInfo:
         info = BankInfo()

@@ -16,12 +16,13 @@ TOL_FP32 = 1e-4
 
 
 def run_stream(gpu, bank, x, chunk, *, peak_window=0, filters_per_lane=0, max_delay=0,
-               want_z=True):
+               want_z=True, time_tile=0):
     import torch
     D, N = x.shape
     zs, pk, am = [], [], []
     with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=chunk, peak_window=peak_window,
-                                 filters_per_lane=filters_per_lane, max_delay=max_delay) as sb:
+                                 filters_per_lane=filters_per_lane, max_delay=max_delay,
+                                 time_tile=time_tile) as sb:
         xd = torch.from_numpy(x).cuda()
         for lo in range(0, N, chunk):
             xc = xd[:, lo:lo + chunk].contiguous()
@@ -30,6 +31,7 @@ def run_stream(gpu, bank, x, chunk, *, peak_window=0, filters_per_lane=0, max_de
                 zs.append(z.cpu().numpy())
             pk.append(p.cpu().numpy()); am.append(a.cpu().numpy())
         torch.cuda.synchronize()
+        assert sb.refresh_info().scan_wait_timeouts == 0
     z = np.concatenate(zs, axis=-1) if want_z else None
     return z, pk, am
 
@@ -48,26 +50,40 @@ def test_tiny_workload_whole_and_chunked(gpu):
             check_peaks(pk[c], am[c], z[..., lo:lo + chunk], z_ref[..., lo:lo + chunk], chunk)
 
 
+@pytest.mark.parametrize("time_tile", [0, 256, 16])
 @pytest.mark.parametrize("chunk", [1, 7, 100, 512, 1000])
-def test_chunk_sizes_agree_with_oracle(gpu, chunk):
+def test_chunk_sizes_agree_with_oracle(gpu, chunk, time_tile):
     rng = np.random.default_rng(100 + chunk)
     bank = synth.draw_filters(rng, np.array([70, 130, 5]))
     n = 3000 if chunk > 1 else 400
     x = rng.standard_normal((2, n)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
-    z, _, _ = run_stream(gpu, bank, x, chunk)
+    z, _, _ = run_stream(gpu, bank, x, chunk, time_tile=time_tile)
     assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
 
 
+@pytest.mark.parametrize("time_tile", [16, 256, 4096, -1])
+def test_time_tiles_on_a_larger_bank(gpu, time_tile):
+    # many slices and tiles: exercises the persistent queue's dependency chains
+    rng = np.random.default_rng(150)
+    bank = synth.draw_filters(rng, rng.integers(50, 900, size=96))
+    x = rng.standard_normal((3, 6144)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    z, pk, am = run_stream(gpu, bank, x, 2048, time_tile=time_tile)
+    assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
+
+
+@pytest.mark.parametrize("time_tile", [0, 256])
 @pytest.mark.parametrize("fpl", [2, 4, 8])
-def test_filters_per_lane_and_slice_boundaries(gpu, fpl):
+def test_filters_per_lane_and_slice_boundaries(gpu, fpl, time_tile):
     # template sizes around the slot/slice boundaries: 64*fpl filters per slice
     counts = np.array([1, 63, 64, 65, 64 * fpl, 64 * fpl + 1, 3 * 64 * fpl - 7, 0, 2])
     rng = np.random.default_rng(200 + fpl)
     bank = synth.draw_filters(rng, counts)
     x = rng.standard_normal((1, 2500)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
-    z, pk, am = run_stream(gpu, bank, x, 2500, filters_per_lane=fpl, peak_window=500)
+    z, pk, am = run_stream(gpu, bank, x, 2500, filters_per_lane=fpl, peak_window=500,
+                           time_tile=time_tile)
     err = oracle.rel_err(z, z_ref)
     nz = np.linalg.norm(z_ref, axis=-1) > 0
     assert err[nz].max() <= TOL_FP32
@@ -83,8 +99,8 @@ def test_delay_extremes_and_history(gpu):
     bank.d[5:10] = 2047
     x = rng.standard_normal((1, 6000)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
-    for chunk, md in ((512, 0), (300, 4000), (6000, 0)):
-        z, _, _ = run_stream(gpu, bank, x, chunk, max_delay=md)
+    for chunk, md, tt in ((512, 0, 0), (300, 4000, 256), (6000, 0, 0), (6000, 0, 512), (300, 8191, 64)):
+        z, _, _ = run_stream(gpu, bank, x, chunk, max_delay=md, time_tile=tt)
         assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
 
 
