@@ -49,6 +49,11 @@ def parse():
     p.add_argument("--no-check", action="store_true")
     p.add_argument("--cpu-templates", type=int, default=1024,
                    help="templates in the oracle's timed sample (full 64-s stream)")
+    p.add_argument("--no-precision", action="store_true",
+                   help="skip the split-bf16 block form vs FP32 scan comparison")
+    p.add_argument("--precision-only", action="store_true")
+    p.add_argument("--precision-reps", type=int, default=5)
+    p.add_argument("--block-len", type=int, default=0, help="0 = sweep 64, 128, 256")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB four times "
                         "(calibrates the HBM byte counters) and exit")
@@ -67,6 +72,61 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 4}), flush=True)
 
 
+def precision_comparison(args, dev):
+    """Split-bf16 block form vs FP32 scan on the precision workload: the 1024-template
+    bank over 3 detector streams of 32 s, one packet per stream; relative SNR error of
+    each against the FP64 oracle on seeded templates."""
+    import torch
+    import oracle
+    from paper_2011_06787_amd import spiir
+    w = synth.precision()
+    bank, x_host = w.bank, w.input()
+    D, N, F, T = w.n_det, w.n_samples, bank.n_filters, bank.n_templates
+    x = torch.from_numpy(x_host).to(dev)
+    z = torch.empty((D, T, N), dtype=torch.complex64, device=dev)
+    pick = sorted(set([0, T - 1]) | set(np.random.default_rng(5).choice(T, 6, replace=False).tolist()))
+    z_ref = oracle.filter(bank.subset(pick), x_host)
+    idx = torch.tensor(pick, device=dev)
+    out = {"workload": "precision: 1024 templates x U{200..800} filters (521,135), 3 detector "
+                       "streams of 32 s at 2048 Hz, one packet per stream",
+           "updates_per_pass": F * D * N}
+    modes = [("fp32_scan", dict(mode=spiir.MODE_FP32_SCAN))]
+    for L in ([args.block_len] if args.block_len else [64, 128, 256]):
+        modes.append((f"bf16_block_L{L}", dict(mode=spiir.MODE_BF16_BLOCK, block_len=L)))
+    for name, kw in modes:
+        t_create = time.perf_counter()
+        sb = spiir.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=N, **kw)
+        t_create = time.perf_counter() - t_create
+        sb.filter_chunk(x, z, want_peaks=False)       # warm-up
+        sb.reset()
+        torch.cuda.synchronize()
+        sb.set_timing(True, capacity=args.precision_reps)
+        t0 = time.perf_counter()
+        for _ in range(args.precision_reps):
+            sb.reset()
+            sb.filter_chunk(x, z, want_peaks=False)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.precision_reps
+        kern_ms, launches = sb.kernel_time()
+        zsel = z.index_select(1, idx).cpu().numpy()
+        err = oracle.rel_err(zsel, z_ref)
+        info = sb.refresh_info()
+        out[name] = {"updates_per_s": F * D * N / wall, "ms_per_pass": wall * 1e3,
+                     "kernel_ms": kern_ms / max(launches, 1),
+                     "rel_err_max": float(err.max()), "rel_err_median": float(np.median(err)),
+                     "create_s": t_create, "device_bytes": info.device_bytes,
+                     "long_pole_filters": info.n_long_pole}
+        log(f"precision {name}: {wall * 1e3:.2f} ms/pass, {F * D * N / wall:.4g} upd/s, "
+            f"rel err max {err.max():.2e}, create {t_create:.1f} s")
+        sb.close()
+        del sb
+        torch.cuda.empty_cache()
+    best = max((k for k in out if k.startswith("bf16_block")), key=lambda k: out[k]["updates_per_s"])
+    out["best_block"] = best
+    out["block_speedup_vs_fp32"] = out[best]["updates_per_s"] / out["fp32_scan"]["updates_per_s"]
+    return out
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -80,6 +140,10 @@ def main():
     import torch
     from paper_2011_06787_amd import spiir
 
+    dev = torch.device("cuda:0")
+    if args.precision_only:
+        print(json.dumps({"precision": precision_comparison(args, dev)}), flush=True)
+        return
     w = synth.realistic()
     bank = w.bank
     chunk = w.chunk
@@ -88,7 +152,6 @@ def main():
     D, T, F = w.n_det, bank.n_templates, bank.n_filters
     log(f"workload {w.name}: T={T} F={F} D={D} N={x_host.shape[1]} chunk={chunk}")
 
-    dev = torch.device("cuda:0")
     x = torch.from_numpy(x_host).to(dev)
     chunks = [x[:, i * chunk:(i + 1) * chunk].contiguous() for i in range(n_chunks)]
     sb = spiir.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=chunk,
@@ -197,6 +260,10 @@ def main():
                       f"of the same bank over the same 64-s stream, {dt:.1f} s wall",
         }
     sb.close()
+    del sb
+    torch.cuda.empty_cache()
+    if not args.no_precision:
+        result["precision"] = precision_comparison(args, dev)
     print(json.dumps(result), flush=True)
 
 

@@ -72,11 +72,13 @@ typedef struct {
     int32_t block_len;        /* block form: time-block length L, 64, 128 or 256; 0 = 128 */
     double long_pole_abs_a;   /* block form: filters with |a_k| above this carry their
                                  block-to-block state in FP64; <= 0 = 0.999 */
+    int32_t ckpt_stride;      /* differentiation: samples per checkpoint segment,
+                                 a multiple of 128; 0 = 2048 */
 } spiir_opts;
 
 /* Fill `opts` with defaults: 1 detector, max_chunk 2048, max_delay 0 (from the bank),
  * one peak window per packet, FP32 scan, 4 filters per lane, no time split, L = 128,
- * 0.999. */
+ * 0.999, checkpoint stride 2048. */
 void spiir_opts_default(spiir_opts *opts);
 
 /*
@@ -149,6 +151,49 @@ spiir_status spiir_filter_chunk(spiir_bank *bank, const float *x, int32_t n, flo
  */
 spiir_status spiir_peaks(const float *z, int64_t rows, int32_t n, int32_t window, float *peak,
                          int32_t *argmax, void *stream);
+
+/*
+ * ---- Differentiation (FP32 scan mode only) ----
+ * For fitting coefficients to a target response (the overlap of Eq. overlap,
+ * Section II.B.1, between a template and the summed filter response).  These
+ * calls run a whole signal from zero state and zero history; they use the bank's
+ * stream buffers, so the stream state is undefined afterwards (call
+ * spiir_bank_reset before streaming again).  Gradients use the convention
+ * dL/dRe(c) + i dL/dIm(c) for a real loss L and complex c (torch's).
+ */
+
+/* Number of complex64 values of the checkpoint buffer for a signal of n samples
+ * (the filter state at the start of every ckpt_stride-sample segment, per detector). */
+spiir_status spiir_ckpt_count(const spiir_bank *bank, int32_t n, int64_t *n_values);
+
+/*
+ * Forward pass over a whole signal from zero state: z as in spiir_filter_chunk.
+ *   x     device float32 [D][n], 1 <= n <= max_chunk
+ *   z     device complex64 [D][T][n]
+ *   ckpt  device complex64 [spiir_ckpt_count], or NULL: states for spiir_backward
+ */
+spiir_status spiir_forward(spiir_bank *bank, const float *x, int32_t n, float *z, float *ckpt,
+                           void *stream);
+
+/*
+ * Reverse-time adjoint: the gradient of a real loss L with respect to every a_k
+ * and b_k, given grad_z = dL/dRe z + i dL/dIm z (device complex64 [D][T][n]) for
+ * the z of spiir_forward on the same x with the same coefficients, and that
+ * call's checkpoints.  With lambda_k[n] = grad_z_t[n] + conj(a_k) lambda_k[n+1]:
+ *   grad_a_k = sum_n lambda_k[n] conj(y_k[n-1]),   grad_b_k = sum_n lambda_k[n] x[n-d_k]
+ * summed over detectors.  Inside each checkpoint segment the states are recomputed
+ * forward (no per-sample storage).
+ *   grad_a, grad_b  device complex64 [F] in the bank's original filter order (overwritten)
+ */
+spiir_status spiir_backward(spiir_bank *bank, const float *x, int32_t n, const float *grad_z,
+                            const float *ckpt, float *grad_a, float *grad_b, void *stream);
+
+/*
+ * Replace the coefficients with device arrays a, b (complex64 [F], original filter
+ * order); delays and layout are kept.  Enqueued on `stream`; the values are not
+ * validated (the caller keeps |a_k| < 1).  FP32 scan mode only.
+ */
+spiir_status spiir_bank_set_coeffs(spiir_bank *bank, const float *a, const float *b, void *stream);
 
 /*
  * Kernel timing (diagnostics for roofline reporting).  While enabled, every

@@ -4,6 +4,6 @@ The compute lives in ``libspiir.so`` (hand-written HIP for gfx950, C ABI in
 ``include/spiir.h``); :mod:`.spiir` is its thin ctypes binding.
 """
 from . import spiir  # noqa: F401
-from .spiir import SpiirBank, SpiirError, peaks  # noqa: F401
+from .spiir import SpiirBank, SpiirError, peaks, spiir_filter  # noqa: F401
 
-__all__ = ["spiir", "SpiirBank", "SpiirError", "peaks"]
+__all__ = ["spiir", "SpiirBank", "SpiirError", "peaks", "spiir_filter"]

@@ -157,7 +157,6 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
     SPIIR_TRY(dev_alloc(bk, &bk.d_slices, std::max<int64_t>(bk.n_slices, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_tmpl_slices, T + 1));
     SPIIR_TRY(dev_alloc(bk, &bk.d_state, lanes * bk.n_det));
-    SPIIR_TRY(dev_alloc(bk, &bk.d_hist, std::max<int64_t>((int64_t)bk.hist_len * bk.n_det, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_partial,
                         std::max<int64_t>((int64_t)bk.n_det * bk.n_slices * bk.max_chunk, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_queue, 1));
@@ -183,8 +182,12 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
 }
 
 spiir_status zero_stream_state(spiir::Bank &bk, hipStream_t s) {
-    SPIIR_HIP(spiir::launch_zero(bk.d_state, round16(bk.n_slots * spiir::kWave * bk.n_det *
-                                                     (int64_t)sizeof(float2)), s));
+    if (bk.mode == SPIIR_MODE_BF16_BLOCK)
+        SPIIR_HIP(spiir::launch_zero(bk.d_state64, round16(std::max<int64_t>(bk.n_fpad, 1) * bk.n_det *
+                                                           (int64_t)sizeof(double2)), s));
+    else
+        SPIIR_HIP(spiir::launch_zero(bk.d_state, round16(bk.n_slots * spiir::kWave * bk.n_det *
+                                                         (int64_t)sizeof(float2)), s));
     if (bk.hist_len > 0)
         SPIIR_HIP(spiir::launch_zero(bk.d_hist,
                                      round16((int64_t)bk.hist_len * bk.n_det * (int64_t)sizeof(float)),
@@ -217,6 +220,7 @@ void spiir_opts_default(spiir_opts *opts) {
     opts->time_tile = 0;
     opts->block_len = 128;
     opts->long_pole_abs_a = 0.999;
+    opts->ckpt_stride = 2048;
 }
 
 const char *spiir_last_error(void) { return g_error.c_str(); }
@@ -248,8 +252,18 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         if (opts.peak_window < 0) return fail(SPIIR_E_INVAL, "peak_window must be >= 0");
         if (opts.mode != SPIIR_MODE_FP32_SCAN && opts.mode != SPIIR_MODE_BF16_BLOCK)
             return fail(SPIIR_E_INVAL, "unknown mode");
-        if (opts.mode == SPIIR_MODE_BF16_BLOCK)
-            return fail(SPIIR_E_UNSUPPORTED, "the split-bf16 block form is not built yet");
+        const int block_len = opts.block_len == 0 ? 128 : opts.block_len;
+        const int ckpt_stride = opts.ckpt_stride == 0 ? 2048 : opts.ckpt_stride;
+        if (ckpt_stride < 128 || ckpt_stride % 128 != 0)
+            return fail(SPIIR_E_INVAL, "ckpt_stride must be a positive multiple of 128");
+        if (opts.mode == SPIIR_MODE_BF16_BLOCK) {
+            if (block_len != 64 && block_len != 128 && block_len != 256)
+                return fail(SPIIR_E_INVAL, "block_len must be 64, 128 or 256");
+            if (opts.max_chunk % block_len != 0)
+                return fail(SPIIR_E_INVAL, "block form: max_chunk must be a multiple of block_len");
+            if (opts.peak_window > 0 && opts.peak_window % block_len != 0)
+                return fail(SPIIR_E_INVAL, "block form: peak_window must be a multiple of block_len");
+        }
         int fpl = opts.filters_per_lane == 0 ? 4 : opts.filters_per_lane;
         if (fpl != 2 && fpl != 4 && fpl != 8)
             return fail(SPIIR_E_INVAL, "filters_per_lane must be 2, 4 or 8");
@@ -289,21 +303,33 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         bk.mode = opts.mode;
         bk.fpl = fpl;
         bk.time_tile = time_tile > 0 ? time_tile : 0;
-        bk.block_len = opts.block_len == 0 ? 128 : opts.block_len;
+        bk.block_len = block_len;
+        bk.ckpt_stride = ckpt_stride;
         bk.long_pole = opts.long_pole_abs_a > 0 ? opts.long_pole_abs_a : 0.999;
         int32_t tile = spiir::kWindowFloats - hist_len - spiir::kSub;
         tile = std::min(tile, bk.max_chunk);
         tile = std::max(spiir::kSub, tile / spiir::kSub * spiir::kSub);
         bk.scan_tile = tile;
         hipStream_t s = static_cast<hipStream_t>(stream);
-        spiir_status st = plan_scan(bk, offsets, a, b, delay, s);
-        if (st == SPIIR_OK) {
-            const hipError_t e = spiir::prepare_scan_fp32(bk);
-            if (e != hipSuccess)
-                st = fail(SPIIR_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+        spiir_status st = dev_alloc(bk, &bk.d_hist, std::max<int64_t>((int64_t)bk.hist_len * bk.n_det, 4));
+        if (st == SPIIR_OK && bk.mode == SPIIR_MODE_BF16_BLOCK) {
+            std::string err;
+            st = spiir::plan_block(bk, offsets, a, b, delay, s, err);
+            if (st != SPIIR_OK) fail(st, err);
+        } else if (st == SPIIR_OK) {
+            st = plan_scan(bk, offsets, a, b, delay, s);
+            if (st == SPIIR_OK) {
+                hipError_t e = spiir::prepare_scan_fp32(bk);
+                // the backward kernel's LDS window (segment + history) must fit
+                if (e == hipSuccess &&
+                    spiir::backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl) <= 160 * 1024)
+                    e = spiir::prepare_backward(bk);
+                if (e != hipSuccess)
+                    st = fail(SPIIR_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+            }
+            if (st == SPIIR_OK) st = zero_queue(bk, s);
         }
         if (st == SPIIR_OK) st = zero_stream_state(bk, s);
-        if (st == SPIIR_OK) st = zero_queue(bk, s);
         if (st == SPIIR_OK) {
             const hipError_t e = hipStreamSynchronize(s);
             if (e != hipSuccess) st = fail(SPIIR_E_HIP, std::string("hipStreamSynchronize: ") +
@@ -401,7 +427,7 @@ spiir_status spiir_bank_get_info(const spiir_bank *h, spiir_bank_info *info) {
     info->time_tile = bk.time_tile;
     info->scan_waves = bk.scan_waves;
     info->block_len = bk.block_len;
-    info->n_long_pole = 0;
+    info->n_long_pole = bk.n_long_pole;
     if (bk.d_queue != nullptr) {
         spiir::ScanQueue q{};
         SPIIR_HIP(hipStreamSynchronize(bk.last_stream));
@@ -424,16 +450,104 @@ spiir_status spiir_filter_chunk(spiir_bank *h, const float *x, int32_t n, float 
     if (peak != nullptr && bk.peak_window > 0 && n % bk.peak_window != 0)
         return fail(SPIIR_E_INVAL, "n must be a multiple of peak_window");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (bk.mode == SPIIR_MODE_BF16_BLOCK) {
+        if (n % bk.block_len != 0)
+            return fail(SPIIR_E_INVAL, "block form: n must be a multiple of block_len=" +
+                                           std::to_string(bk.block_len));
+        bk.last_stream = s;
+        float2 *zz = z != nullptr ? reinterpret_cast<float2 *>(z) : bk.d_zbuf;
+        const bool timing = bk.timed < (int64_t)bk.ev_start.size();
+        if (timing) SPIIR_HIP(hipEventRecord(bk.ev_start[bk.timed], s));
+        SPIIR_HIP(spiir::launch_block_bf16(bk, x, n, zz, s));
+        if (timing) {
+            SPIIR_HIP(hipEventRecord(bk.ev_stop[bk.timed], s));
+            ++bk.timed;
+        }
+        SPIIR_HIP(spiir::launch_hist_update(bk, x, n, s));
+        if (peak != nullptr) {
+            const int32_t window = bk.peak_window > 0 ? bk.peak_window : n;
+            SPIIR_HIP(spiir::launch_peaks(zz, (int64_t)bk.n_det * bk.n_templates, n, window, peak,
+                                          argmax, s));
+        }
+        return SPIIR_OK;
+    }
     bk.last_stream = s;
     const bool timing = bk.timed < (int64_t)bk.ev_start.size();
     if (timing) SPIIR_HIP(hipEventRecord(bk.ev_start[bk.timed], s));
-    SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, s));
+    SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, nullptr, s));
     if (timing) {
         SPIIR_HIP(hipEventRecord(bk.ev_stop[bk.timed], s));
         ++bk.timed;
     }
     SPIIR_HIP(spiir::launch_hist_update(bk, x, n, s));
     SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), peak, argmax, s));
+    return SPIIR_OK;
+}
+
+spiir_status spiir_ckpt_count(const spiir_bank *h, int32_t n, int64_t *n_values) {
+    if (h == nullptr || n_values == nullptr) return fail(SPIIR_E_INVAL, "bank or n_values is NULL");
+    const spiir::Bank &bk = h->bk;
+    if (bk.mode != SPIIR_MODE_FP32_SCAN)
+        return fail(SPIIR_E_UNSUPPORTED, "differentiation needs the FP32 scan mode");
+    if (n < 0) return fail(SPIIR_E_INVAL, "n must be >= 0");
+    const int64_t n_seg = (n + bk.ckpt_stride - 1) / bk.ckpt_stride;
+    *n_values = (int64_t)bk.n_det * n_seg * bk.n_slots * spiir::kWave;
+    return SPIIR_OK;
+}
+
+namespace {
+spiir_status check_diff_call(const spiir::Bank &bk, const float *x, int32_t n) {
+    if (bk.mode != SPIIR_MODE_FP32_SCAN)
+        return fail(SPIIR_E_UNSUPPORTED, "differentiation needs the FP32 scan mode");
+    if (n < 1 || n > bk.max_chunk)
+        return fail(SPIIR_E_INVAL, "n must be in [1, max_chunk=" + std::to_string(bk.max_chunk) + "]");
+    if (x == nullptr) return fail(SPIIR_E_INVAL, "x is NULL");
+    return SPIIR_OK;
+}
+}  // namespace
+
+spiir_status spiir_forward(spiir_bank *h, const float *x, int32_t n, float *z, float *ckpt,
+                           void *stream) {
+    if (h == nullptr) return fail(SPIIR_E_INVAL, "bank is NULL");
+    spiir::Bank &bk = h->bk;
+    SPIIR_TRY(check_diff_call(bk, x, n));
+    if (z == nullptr) return fail(SPIIR_E_INVAL, "z is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bk.last_stream = s;
+    SPIIR_TRY(zero_stream_state(bk, s));
+    SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, reinterpret_cast<float2 *>(ckpt), s));
+    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), nullptr, nullptr, s));
+    return SPIIR_OK;
+}
+
+spiir_status spiir_backward(spiir_bank *h, const float *x, int32_t n, const float *grad_z,
+                            const float *ckpt, float *grad_a, float *grad_b, void *stream) {
+    if (h == nullptr) return fail(SPIIR_E_INVAL, "bank is NULL");
+    spiir::Bank &bk = h->bk;
+    SPIIR_TRY(check_diff_call(bk, x, n));
+    if (grad_z == nullptr || ckpt == nullptr || grad_a == nullptr || grad_b == nullptr)
+        return fail(SPIIR_E_INVAL, "grad_z, ckpt, grad_a and grad_b must be non-NULL");
+    if (spiir::backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl) > 160 * 1024)
+        return fail(SPIIR_E_UNSUPPORTED, "ckpt_stride + max_delay too large for the adjoint window");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bk.last_stream = s;
+    SPIIR_HIP(spiir::launch_backward(bk, x, n, reinterpret_cast<const float2 *>(grad_z),
+                                     reinterpret_cast<const float2 *>(ckpt),
+                                     reinterpret_cast<float2 *>(grad_a),
+                                     reinterpret_cast<float2 *>(grad_b), s));
+    return SPIIR_OK;
+}
+
+spiir_status spiir_bank_set_coeffs(spiir_bank *h, const float *a, const float *b, void *stream) {
+    if (h == nullptr) return fail(SPIIR_E_INVAL, "bank is NULL");
+    spiir::Bank &bk = h->bk;
+    if (bk.mode != SPIIR_MODE_FP32_SCAN)
+        return fail(SPIIR_E_UNSUPPORTED, "spiir_bank_set_coeffs needs the FP32 scan mode");
+    if (bk.n_filters > 0 && (a == nullptr || b == nullptr)) return fail(SPIIR_E_INVAL, "a or b is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bk.last_stream = s;
+    SPIIR_HIP(spiir::launch_set_coeffs(bk, reinterpret_cast<const float2 *>(a),
+                                       reinterpret_cast<const float2 *>(b), s));
     return SPIIR_OK;
 }
 

@@ -25,6 +25,28 @@ struct ScanQueue {
     uint32_t error;  // sticky count of dependency waits that hit their bound
 };
 
+// Block form: one row tile of the input-to-state product (16 filters of one
+// template, sorted by delay) and its band of input offsets.
+struct WTile {
+    int32_t tmpl;
+    int32_t f0;        // first filter of the tile, in the template's delay order
+    int32_t sigma_lo;  // first input offset (relative to the block start), multiple of 16
+    int32_t nks;       // K steps of 16 offsets
+    int64_t a_off;     // bf16 offset of the tile's operand blocks
+    int64_t g0;        // first filter of the tile in the bank's sorted-padded order
+};
+
+// Block form: per-template operands of the output product z = [P | M] [Y; H].
+struct BTemplate {
+    int32_t fpad;      // filters rounded up to 16
+    int32_t nks_p;     // K steps of the state part (2*fpad/16)
+    int32_t nks_m;     // K steps of the input part ((L - sigma_lo)/16)
+    int32_t sigma_lo;  // first input offset of the input part, multiple of 16
+    int64_t a_off;     // bf16 offset of the template's operand blocks
+    int64_t y_off;     // element offset of the template's state rows (per detector)
+    int64_t g0;        // first filter of the template in the sorted-padded order
+};
+
 // One FP32-scan work unit: up to 64 * filters_per_lane filters of one template.
 // Its filters occupy `n_slots` consecutive slots of 64 lanes starting at `slot_base`.
 struct Slice {
@@ -49,6 +71,7 @@ struct Bank {
     int32_t scan_tile = 2048;  // samples per LDS input window of the one-shot FP32 scan
     int32_t time_tile = 256;   // samples per work item of the persistent scan; 0 = one-shot
     int32_t scan_waves = 0;    // resident waves of the persistent scan (grid size)
+    int32_t ckpt_stride = 2048;  // differentiation: samples per checkpoint segment
 
     // FP32 scan layout
     int32_t n_slices = 0;
@@ -66,6 +89,24 @@ struct Bank {
     uint32_t *d_flags = nullptr; // [D][n_slices]: tiles completed (epoch-relative)
     int32_t *d_order = nullptr;  // [D*n_slices]: det*n_slices + slice, largest slices first
 
+    // block form (split-bf16 matrix-core products)
+    int32_t hist_pad = 0;        // history samples kept in the split input, multiple of 16
+    int32_t n_wtiles = 0;
+    int64_t n_fpad = 0;          // filters in sorted-padded order
+    int64_t y_per_det = 0;       // state-row elements per detector (NBmax * sum 2*fpad)
+    int32_t n_long_pole = 0;
+    WTile *d_wtiles = nullptr;
+    BTemplate *d_btmpl = nullptr;
+    uint16_t *d_wa = nullptr;    // input-to-state operand blocks (bf16 hi/lo)
+    uint16_t *d_pa = nullptr;    // output operand blocks (bf16 hi/lo)
+    double2 *d_aL = nullptr;     // [n_fpad] a^L in FP64
+    int32_t *d_lp = nullptr;     // [n_fpad] 1 if |a| > long_pole
+    double2 *d_state64 = nullptr;  // [D][n_fpad] carried state
+    uint16_t *d_yt = nullptr;    // [2][D][y_per_det]: state entering each block, bf16 hi / lo planes
+    int64_t xs_stride = 0;       // per-detector length of the split input
+    uint16_t *d_xs = nullptr;    // [2][D][xs_stride]: input from -hist_pad, bf16 hi / lo planes
+    float2 *d_zbuf = nullptr;    // [D][T][max_chunk] when the caller passes no z
+
     int64_t device_bytes = 0;
     hipStream_t last_stream = nullptr;
 
@@ -79,12 +120,21 @@ struct Bank {
 size_t scan_fp32_lds_bytes(int32_t tile, int32_t hist_len);
 size_t scan_persistent_lds_bytes(int32_t tile, int32_t hist_len);
 hipError_t prepare_scan_fp32(Bank &bk);
-hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, hipStream_t s);
+hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, float2 *ckpt,
+                            hipStream_t s);
+size_t backward_lds_bytes(int32_t stride, int32_t hist_len, int32_t fpl);
+hipError_t prepare_backward(const Bank &bk);
+hipError_t launch_backward(const Bank &bk, const float *x, int32_t n, const float2 *gz,
+                           const float2 *ckpt, float2 *grad_a, float2 *grad_b, hipStream_t s);
+hipError_t launch_set_coeffs(const Bank &bk, const float2 *a, const float2 *b, hipStream_t s);
 hipError_t launch_hist_update(const Bank &bk, const float *x, int32_t n, hipStream_t s);
 hipError_t launch_reduce_peaks(const Bank &bk, int32_t n, float2 *z, float *peak,
                                int32_t *argmax, hipStream_t s);
 hipError_t launch_peaks(const float2 *z, int64_t rows, int32_t n, int32_t window, float *peak,
                         int32_t *argmax, hipStream_t s);
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t s);
+hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *z, hipStream_t s);
+spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const float *b,
+                        const int32_t *delay, hipStream_t s, std::string &err);
 
 }  // namespace spiir

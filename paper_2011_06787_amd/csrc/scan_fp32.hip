@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     float2 *__restrict__ state, const Slice *__restrict__ slices, int32_t n_slices,
     int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
     int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, int32_t tile_len,
-    int32_t win_floats) {
+    int32_t win_floats, float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg) {
     extern __shared__ float smem[];
     float *win = smem;
     const int wave = threadIdx.x / kWave;
@@ -150,6 +150,13 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     const float *xd = x + (int64_t)det * n;
     const float *hd = hist + (int64_t)det * hist_len;
     float2 *pout = partial + ((int64_t)det * n_slices + sidx) * part_stride;
+    // optional checkpoints: the state entering every ckpt_stride-sample segment
+    float2 *ck = ckpt != nullptr ? ckpt + (int64_t)det * n_seg * lanes_total : nullptr;
+    if (ck != nullptr && active) {
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j)
+            if (j < m) ck[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+    }
 
     for (int n0 = 0; n0 < n; n0 += tile_len) {
         const int T = min(tile_len, n - n0);
@@ -158,9 +165,17 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
         __syncthreads();
         if (!active) continue;
         int s0 = 0;
-        for (; s0 + kSub <= T; s0 += kSub)
+        for (; s0 + kSub <= T; s0 += kSub) {
             sub_tile<MAXM, false>(win, red, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
                                   pout + n0 + s0);
+            const int e = n0 + s0 + kSub;
+            if (ck != nullptr && e % ckpt_stride == 0 && e < n) {
+                float2 *cs = ck + (int64_t)(e / ckpt_stride) * lanes_total;
+#pragma unroll
+                for (int j = 0; j < MAXM; ++j)
+                    if (j < m) cs[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+            }
+        }
         if (s0 < T)
             sub_tile<MAXM, true>(win, red, lane, m, s0, T - s0, ar, ai, br, bi, base, yr, yi,
                                  pout + n0 + s0);
@@ -360,9 +375,9 @@ hipError_t prepare_fpl(Bank &bk) {
 }
 
 template <int MAXM>
-void launch_fpl(const Bank &bk, const float *x, int32_t n, hipStream_t s) {
+void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStream_t s) {
     const int64_t lanes = bk.n_slots * kWave;
-    if (bk.time_tile > 0) {
+    if (bk.time_tile > 0 && ckpt == nullptr) {
         const int32_t win_floats = ((bk.time_tile + bk.hist_len + kSub) + 3) & ~3;
         const int64_t items = (int64_t)((n + bk.time_tile - 1) / bk.time_tile) * bk.n_det *
                               bk.n_slices;
@@ -379,7 +394,8 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, hipStream_t s) {
         hipLaunchKernelGGL(scan_fp32_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
                            scan_fp32_lds_bytes(tile, bk.hist_len), s, bk.d_a, bk.d_b, bk.d_delay,
                            bk.d_state, bk.d_slices, bk.n_slices, lanes, x, n, bk.d_hist,
-                           bk.hist_len, bk.d_partial, bk.max_chunk, tile, win_floats);
+                           bk.hist_len, bk.d_partial, bk.max_chunk, tile, win_floats, ckpt,
+                           bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride);
     }
 }
 
@@ -394,12 +410,12 @@ hipError_t prepare_scan_fp32(Bank &bk) {
     }
 }
 
-hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, hipStream_t s) {
+hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStream_t s) {
     if (n <= 0 || bk.n_slices == 0) return hipSuccess;
     switch (bk.fpl) {
-    case 2: launch_fpl<2>(bk, x, n, s); break;
-    case 4: launch_fpl<4>(bk, x, n, s); break;
-    case 8: launch_fpl<8>(bk, x, n, s); break;
+    case 2: launch_fpl<2>(bk, x, n, ckpt, s); break;
+    case 4: launch_fpl<4>(bk, x, n, ckpt, s); break;
+    case 8: launch_fpl<8>(bk, x, n, ckpt, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -29,7 +29,8 @@ MODE_BF16_BLOCK = 1
 EXPORTS = (
     "spiir_opts_default", "spiir_bank_create", "spiir_bank_destroy", "spiir_bank_reset",
     "spiir_bank_get_info", "spiir_filter_chunk", "spiir_peaks", "spiir_last_error",
-    "spiir_bank_set_timing", "spiir_bank_kernel_time",
+    "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count", "spiir_forward",
+    "spiir_backward", "spiir_bank_set_coeffs",
 )
 
 
@@ -50,6 +51,7 @@ class Opts(ctypes.Structure):
         ("time_tile", ctypes.c_int32),
         ("block_len", ctypes.c_int32),
         ("long_pole_abs_a", ctypes.c_double),
+        ("ckpt_stride", ctypes.c_int32),
     ]
 
 
@@ -91,11 +93,16 @@ def load():
     lib.spiir_bank_set_timing.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
     lib.spiir_bank_kernel_time.argtypes = [_P, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]
+    lib.spiir_ckpt_count.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+    lib.spiir_forward.argtypes = [_P, _P, ctypes.c_int32, _P, _P, _P]
+    lib.spiir_backward.argtypes = [_P, _P, ctypes.c_int32, _P, _P, _P, _P, _P]
+    lib.spiir_bank_set_coeffs.argtypes = [_P, _P, _P, _P]
     lib.spiir_last_error.argtypes = []
     lib.spiir_last_error.restype = ctypes.c_char_p
     for name in ("spiir_bank_create", "spiir_bank_destroy", "spiir_bank_reset",
                  "spiir_bank_get_info", "spiir_filter_chunk", "spiir_peaks",
-                 "spiir_bank_set_timing", "spiir_bank_kernel_time"):
+                 "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count",
+                 "spiir_forward", "spiir_backward", "spiir_bank_set_coeffs"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -136,7 +143,7 @@ class SpiirBank:
     def __init__(self, offsets, a, b, delay, *, n_detectors: int = 1, max_chunk: int = 2048,
                  max_delay: int = 0, peak_window: int = 0, mode: int = MODE_FP32_SCAN,
                  filters_per_lane: int = 0, time_tile: int = 0, block_len: int = 0,
-                 long_pole_abs_a: float = 0.999, stream=None):
+                 long_pole_abs_a: float = 0.999, ckpt_stride: int = 0, stream=None):
         lib = load()
         self._offsets = np.ascontiguousarray(offsets, dtype=np.int32)
         self._a = np.ascontiguousarray(a, dtype=np.complex64)
@@ -146,6 +153,7 @@ class SpiirBank:
         o.n_detectors, o.max_chunk, o.max_delay = n_detectors, max_chunk, max_delay
         o.peak_window, o.mode, o.filters_per_lane = peak_window, mode, filters_per_lane
         o.time_tile, o.block_len, o.long_pole_abs_a = time_tile, block_len, long_pole_abs_a
+        o.ckpt_stride = ckpt_stride
         self.opts = o
         h = _P()
         st = lib.spiir_bank_create(int(self._offsets.shape[0] - 1),
@@ -208,6 +216,48 @@ class SpiirBank:
         _check("spiir_filter_chunk", st)
         return z, peak, argmax
 
+    # ---- differentiation (FP32 scan mode) ----
+    def ckpt_count(self, n: int) -> int:
+        cnt = ctypes.c_int64()
+        _check("spiir_ckpt_count", load().spiir_ckpt_count(self._h, int(n), ctypes.byref(cnt)))
+        return cnt.value
+
+    def forward(self, x, z=None, ckpt=None, stream=None):
+        """Whole-signal forward from zero state; returns (z, checkpoints)."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 2
+        n = int(x.shape[1])
+        if z is None:
+            z = torch.empty((self.n_detectors, self.n_templates, n), dtype=torch.complex64,
+                            device=x.device)
+        if ckpt is None:
+            ckpt = torch.empty(self.ckpt_count(n), dtype=torch.complex64, device=x.device)
+        _check("spiir_forward", load().spiir_forward(self._h, x.data_ptr(), n, z.data_ptr(),
+                                                       ckpt.data_ptr(), _stream_ptr(stream)))
+        return z, ckpt
+
+    def backward(self, x, grad_z, ckpt, grad_a=None, grad_b=None, stream=None):
+        """Gradients (complex64 [F], original filter order) of a loss with dL/dz = grad_z."""
+        import torch
+        assert grad_z.dtype == torch.complex64 and grad_z.is_contiguous()
+        n = int(x.shape[1])
+        F = int(self._offsets[-1])
+        if grad_a is None:
+            grad_a = torch.empty(F, dtype=torch.complex64, device=x.device)
+            grad_b = torch.empty(F, dtype=torch.complex64, device=x.device)
+        _check("spiir_backward", load().spiir_backward(
+            self._h, x.data_ptr(), n, grad_z.data_ptr(), ckpt.data_ptr(), grad_a.data_ptr(),
+            grad_b.data_ptr(), _stream_ptr(stream)))
+        return grad_a, grad_b
+
+    def set_coeffs(self, a, b, stream=None):
+        """Load coefficients from cuda complex64 tensors [F] (original filter order)."""
+        import torch
+        assert a.dtype == torch.complex64 and b.dtype == torch.complex64
+        a = a.contiguous(); b = b.contiguous()
+        _check("spiir_bank_set_coeffs", load().spiir_bank_set_coeffs(
+            self._h, a.data_ptr(), b.data_ptr(), _stream_ptr(stream)))
+
     def set_timing(self, enable: bool, capacity: int = 4096):
         """Bracket the main filtering kernel with HIP events (see spiir.h)."""
         _check("spiir_bank_set_timing",
@@ -255,3 +305,43 @@ def peaks(z, window: int, peak=None, argmax=None, stream=None) -> Tuple["object"
                             _stream_ptr(stream))
     _check("spiir_peaks", st)
     return peak, argmax
+
+
+def _make_autograd():
+    import torch
+
+    class SpiirFilterFn(torch.autograd.Function):
+        """z = SPIIR bank(a, b) applied to x from zero state, differentiable in a and b.
+
+        The backward pass is the library's reverse-time adjoint scan
+        (``spiir_backward``) with checkpointed states.
+        """
+
+        @staticmethod
+        def forward(ctx, a, b, x, bank):
+            bank.set_coeffs(a.detach(), b.detach())
+            z, ckpt = bank.forward(x)
+            ctx.save_for_backward(a.detach(), b.detach(), x, ckpt)
+            ctx.bank = bank
+            return z
+
+        @staticmethod
+        def backward(ctx, grad_z):
+            a, b, x, ckpt = ctx.saved_tensors
+            bank = ctx.bank
+            bank.set_coeffs(a, b)
+            ga, gb = bank.backward(x, grad_z.contiguous(), ckpt)
+            return ga, gb, None, None
+
+    return SpiirFilterFn
+
+
+_autograd_fn = None
+
+
+def spiir_filter(a, b, x, bank: SpiirBank):
+    """Differentiable SNR series z[D][T][n] of the bank with coefficients (a, b)."""
+    global _autograd_fn
+    if _autograd_fn is None:
+        _autograd_fn = _make_autograd()
+    return _autograd_fn.apply(a, b, x, bank)

@@ -1,0 +1,112 @@
+"""GPU parity of the split-bf16 time-blocked form against the FP64 oracle.
+
+Tolerance: relative SNR error per (detector, template) at most 1e-3 for the
+split-bf16 block form (the products run as hi*hi + hi*lo + lo*hi in bf16 with
+FP32 accumulation, the block-to-block carry in FP64 for |a| > 0.999).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import check_peaks
+
+pytestmark = pytest.mark.gpu
+
+TOL_BF16 = 1e-3
+
+
+def run_block(gpu, bank, x, chunk, *, block_len=128, peak_window=0, want_z=True,
+              long_pole=0.999):
+    import torch
+    D, N = x.shape
+    zs, pk, am = [], [], []
+    with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=chunk, peak_window=peak_window,
+                                 mode=gpu.MODE_BF16_BLOCK, block_len=block_len,
+                                 long_pole_abs_a=long_pole) as sb:
+        xd = torch.from_numpy(x).cuda()
+        for lo in range(0, N, chunk):
+            z, p, a = sb.filter_chunk(xd[:, lo:lo + chunk].contiguous(), want_z=want_z)
+            if want_z:
+                zs.append(z.cpu().numpy())
+            pk.append(p.cpu().numpy()); am.append(a.cpu().numpy())
+        torch.cuda.synchronize()
+        info = sb.refresh_info()
+    return (np.concatenate(zs, axis=-1) if want_z else None), pk, am, info
+
+
+@pytest.mark.parametrize("block_len", [64, 128, 256])
+def test_block_form_small_bank(gpu, block_len):
+    rng = np.random.default_rng(1000 + block_len)
+    bank = synth.draw_filters(rng, np.array([37, 5, 130, 16, 1]))
+    x = rng.standard_normal((2, 8 * 1024)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    z, pk, am, info = run_block(gpu, bank, x, 2048, block_len=block_len)
+    err = oracle.rel_err(z, z_ref)
+    print(f"L={block_len}: max rel err {err.max():.3e}, long-pole filters {info.n_long_pole}")
+    assert err.max() <= TOL_BF16
+    for c in range(4):
+        sl = slice(c * 2048, (c + 1) * 2048)
+        check_peaks(pk[c], am[c], z[..., sl], z_ref[..., sl], 2048)
+
+
+def test_block_form_streaming_equals_whole(gpu):
+    rng = np.random.default_rng(1100)
+    bank = synth.draw_filters(rng, rng.integers(1, 200, size=9))
+    x = rng.standard_normal((1, 6 * 512)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    z_whole, _, _, _ = run_block(gpu, bank, x, 6 * 512)
+    z_chunks, _, _, _ = run_block(gpu, bank, x, 512)
+    assert oracle.rel_err(z_whole, z_ref).max() <= TOL_BF16
+    assert oracle.rel_err(z_chunks, z_ref).max() <= TOL_BF16
+
+
+def test_long_pole_carry_in_fp64(gpu):
+    # every filter with |a| close to 1: the FP64 carry path; also all-FP32 for contrast
+    rng = np.random.default_rng(1200)
+    bank = synth.draw_filters(rng, np.array([64, 64]), tau_range=(2.0, 4.0))
+    x = rng.standard_normal((1, 32768)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    z, _, _, info = run_block(gpu, bank, x, 32768)
+    assert info.n_long_pole == int(np.sum(np.abs(bank.a.astype(np.complex128)) > 0.999))
+    assert info.n_long_pole > 0
+    assert oracle.rel_err(z, z_ref).max() <= TOL_BF16
+
+
+def test_block_form_empty_template_and_zero_delay(gpu):
+    rng = np.random.default_rng(1300)
+    bank = synth.draw_filters(rng, np.array([20, 0, 3]), max_delay=0)
+    x = rng.standard_normal((1, 1024)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    z, _, _, _ = run_block(gpu, bank, x, 1024, block_len=64)
+    assert np.all(z[:, 1] == 0)
+    nz = [0, 2]
+    assert oracle.rel_err(z[:, nz], z_ref[:, nz]).max() <= TOL_BF16
+
+
+def test_block_form_rejects_ragged_packets(gpu):
+    import torch
+    rng = np.random.default_rng(1400)
+    bank = synth.draw_filters(rng, np.array([8]))
+    with gpu.SpiirBank.from_bank(bank, max_chunk=1024, mode=gpu.MODE_BF16_BLOCK) as sb:
+        with pytest.raises(gpu.SpiirError):
+            sb.filter_chunk(torch.zeros((1, 1000), device="cuda"))
+    with pytest.raises(gpu.SpiirError):
+        gpu.SpiirBank.from_bank(bank, max_chunk=1000, mode=gpu.MODE_BF16_BLOCK)
+
+
+def test_precision_workload_full_size_sampled(gpu):
+    """The precision workload (1024-template bank, 3 detector streams of 32 s) in one
+    packet per detector; sampled templates checked against the oracle."""
+    w = synth.precision()
+    x = w.input()
+    z, pk, am, info = run_block(gpu, w.bank, x, w.n_samples)
+    pick = sorted(set([0, w.bank.n_templates - 1]) |
+                  set(np.random.default_rng(5).choice(w.bank.n_templates, 6, replace=False).tolist()))
+    z_ref = oracle.filter(w.bank.subset(pick), x)
+    err = oracle.rel_err(z[:, pick], z_ref)
+    print(f"precision workload: max rel err {err.max():.3e}, median {np.median(err):.3e}, "
+          f"long-pole filters {info.n_long_pole}")
+    assert err.max() <= TOL_BF16
+    n_win, n_amb, _ = check_peaks(pk[0][:, pick], am[0][:, pick], z[:, pick], z_ref, w.n_samples)
+    print(f"argmax windows {n_win}, ambiguous {n_amb}")
