@@ -65,15 +65,101 @@ __global__ void split_input_kernel(const float *__restrict__ x, int32_t n,
     }
 }
 
-// One wave per (tile of 16 filters, detector): S for all blocks, 32 blocks per MFMA
-// column tile, then the carry along the blocks by 16 lanes (one filter each).
+// Block-to-block carry of one chunk of kChunk blocks for the lane's filter f and its
+// group q of kChunk/4 consecutive blocks:  Y[b+1] = A Y[b] + S[b]  (A = a^L).
+// A two-level scan: every lane runs its group from a zero state, the four group
+// totals are combined through LDS (Ystart[q+1] = A^len Ystart[q] + T[q]), and each
+// lane then adds A^c Ystart[q] to its local states.  The state entering every block
+// is written as bf16 hi + lo.  R is double for long-pole filters, float otherwise.
+constexpr int kChunk = 64;
+constexpr int kGroup = kChunk / 4;
+
+template <typename R>
+struct C2 {
+    R r, i;
+};
+
+template <typename R>
+__device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
+    return C2<R>{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+
+template <typename R>
+__device__ __forceinline__ C2<R> cfma(C2<R> a, C2<R> b, C2<R> c) {   // a*b + c
+    return C2<R>{a.r * b.r - a.i * b.i + c.r, a.r * b.i + a.i * b.r + c.i};
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo_half, float hi_half) {
+    return (uint32_t)bf16_bits(__float2bfloat16(lo_half)) |
+           ((uint32_t)bf16_bits(__float2bfloat16(hi_half)) << 16);
+}
+
+// write Y (state entering block) as hi and lo planes: (re, im) pairs as 32-bit stores
+__device__ __forceinline__ void store_split(uint32_t *yh, uint32_t *yl, float yr, float yi) {
+    const float hr = __bfloat162float(__float2bfloat16(yr));
+    const float hi = __bfloat162float(__float2bfloat16(yi));
+    *yh = pack_bf16(yr, yi);
+    *yl = pack_bf16(yr - hr, yi - hi);
+}
+
+template <typename R>
+__device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R> (*tot)[16],
+                                            int f, int q, int valid_cols, C2<R> A, C2<R> &y_prev,
+                                            uint32_t *yh, uint32_t *yl, int64_t row_len2,
+                                            int64_t col0) {
+    // local scan of the group from zero
+    const int c_lo = q * kGroup;
+    const int len = max(0, min(kGroup, valid_cols - c_lo));
+    C2<R> loc[kGroup];
+    C2<R> y{0, 0};
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+        loc[c] = y;   // local state entering block c_lo + c
+        if (c < len) {
+            const C2<R> sv{(R)sl[2 * f][c_lo + c], (R)sl[2 * f + 1][c_lo + c]};
+            y = cfma(A, y, sv);
+        }
+    }
+    tot[q][f] = y;
+    // one wave per workgroup and the four lanes of a filter take the same branch, so
+    // a wave-level LDS ordering fence (no barrier) is enough here
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    // combine the group totals: state entering each group, and the chunk's exit state
+    C2<R> ystart = y_prev, ynext = y_prev;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        const int lq = max(0, min(kGroup, valid_cols - qq * kGroup));
+        C2<R> p{1, 0};
+        for (int k = 0; k < lq; ++k) p = cmul(p, A);   // A^lq
+        if (qq == q) ystart = ynext;
+        ynext = cfma(p, ynext, tot[qq][f]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    y_prev = ynext;
+    // states entering the group's blocks
+    C2<R> pw = ystart;
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+        if (c < len) {
+            const float yr = (float)(pw.r + loc[c].r), yi = (float)(pw.i + loc[c].i);
+            const int64_t o = (col0 + c_lo + c) * row_len2;
+            store_split(yh + o, yl + o, yr, yi);
+            pw = cmul(A, pw);
+        }
+    }
+}
+
+// One wave per (tile of 16 filters, detector): S for all blocks, kChunk blocks (two
+// 32-column MFMA tiles sharing each A fragment) per pass, then the carry.
 __global__ __launch_bounds__(kWave) void block_state_kernel(
     const WTile *__restrict__ tiles, const BTemplate *__restrict__ tmpls,
     const uint16_t *__restrict__ wa, const uint16_t *__restrict__ xs, int64_t xs_stride,
     int32_t hist_pad, int32_t n_det, int32_t L, int32_t nb, int32_t nb_max,
     const double2 *__restrict__ aL, const int32_t *__restrict__ lp, double2 *__restrict__ state,
     int64_t n_fpad, uint16_t *__restrict__ yt, int64_t y_per_det) {
-    __shared__ float sl[32][33];
+    __shared__ float sl[32][kChunk + 1];
+    __shared__ C2<double> tot64[4][16];
+    __shared__ C2<float> tot32[4][16];
     const int lane = threadIdx.x;
     const WTile tl = tiles[blockIdx.x];
     const int det = blockIdx.y;
@@ -84,155 +170,184 @@ __global__ __launch_bounds__(kWave) void block_state_kernel(
     const int kg = (lane / 32) * 8;
     const uint16_t *ap = wa + tl.a_off + (lane % 32) * 16 + kg;
 
-    // carried state and transition of this lane's filter (lanes 0..15)
-    const int64_t gf = tl.g0 + (lane & 15);
-    double2 y = make_double2(0.0, 0.0);
-    double2 t = make_double2(0.0, 0.0);
-    bool long_pole = false;
-    if (lane < 16) {
-        y = state[(int64_t)det * n_fpad + gf];
-        t = aL[gf];
-        long_pole = lp[gf] != 0;
-    }
-    uint16_t *yh = yt + (int64_t)det * y_per_det + bt.y_off;
-    uint16_t *yl = yh + (int64_t)n_det * y_per_det;
-    const int64_t row_len = 2 * (int64_t)bt.fpad;
+    // carry lanes: filter f of the tile, group q of the chunk's blocks
+    const int f = lane & 15;
+    const int q = lane >> 4;
+    const int64_t gf = tl.g0 + f;
+    const double2 ys = state[(int64_t)det * n_fpad + gf];
+    const double2 ta = aL[gf];
+    const bool long_pole = lp[gf] != 0;
+    C2<double> y64{ys.x, ys.y};
+    C2<float> y32{(float)ys.x, (float)ys.y};
+    const C2<double> A64{ta.x, ta.y};
+    const C2<float> A32{(float)ta.x, (float)ta.y};
+    const int64_t row_len2 = bt.fpad;   // 32-bit (re, im) pairs per block row
+    uint32_t *yh = reinterpret_cast<uint32_t *>(yt + (int64_t)det * y_per_det + bt.y_off) + tl.f0 + f;
+    uint32_t *yl = reinterpret_cast<uint32_t *>(yt + (int64_t)(n_det + det) * y_per_det + bt.y_off) +
+                   tl.f0 + f;
 
-    for (int c0 = 0; c0 < nb; c0 += 32) {
-        const int b = c0 + col;
-        const bool valid = b < nb;
-        f32x16 acc = {};
-        const int64_t pbase = (int64_t)b * L + tl.sigma_lo + kg;
+    for (int c0 = 0; c0 < nb; c0 += kChunk) {
+        f32x16 acc[2] = {};
+        bool valid[2];
+        int64_t pbase[2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int b = c0 + ct * 32 + col;
+            valid[ct] = b < nb;
+            pbase[ct] = (int64_t)(valid[ct] ? b : 0) * L + tl.sigma_lo + kg;
+        }
         for (int ks = 0; ks < tl.nks; ++ks) {
             const bf16x8 ah = load8(ap + (int64_t)ks * 1024);
             const bf16x8 al = load8(ap + (int64_t)ks * 1024 + 512);
-            bf16x8 bh = {}, bl = {};
-            if (valid) {
-                bh = load8(xh + pbase + 16 * ks);
-                bl = load8(xl + pbase + 16 * ks);
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                bf16x8 bh = {}, bl = {};
+                if (valid[ct]) {
+                    bh = load8(xh + pbase[ct] + 16 * ks);
+                    bl = load8(xl + pbase[ct] + 16 * ks);
+                }
+                acc[ct] = mma3(ah, al, bh, bl, acc[ct]);
             }
-            acc = mma3(ah, al, bh, bl, acc);
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sl[8 * (i / 4) + 4 * (lane / 32) + (i % 4)][col] = acc[i];
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                sl[8 * (i / 4) + 4 * (lane / 32) + (i % 4)][ct * 32 + col] = acc[ct][i];
         __syncthreads();
-        if (lane < 16) {
-            const int cmax = min(32, nb - c0);
-            for (int cc = 0; cc < cmax; ++cc) {
-                const int bb = c0 + cc;
-                // state entering block bb, split into bf16 hi + lo
-                const float yr = (float)y.x, yi = (float)y.y;
-                const __hip_bfloat16 hr = __float2bfloat16(yr), hi_ = __float2bfloat16(yi);
-                const __hip_bfloat16 lr = __float2bfloat16(yr - __bfloat162float(hr));
-                const __hip_bfloat16 li = __float2bfloat16(yi - __bfloat162float(hi_));
-                const int64_t o = (int64_t)bb * row_len + 2 * (int64_t)(tl.f0 + lane);
-                yh[o] = bf16_bits(hr);
-                yh[o + 1] = bf16_bits(hi_);
-                yl[o] = bf16_bits(lr);
-                yl[o + 1] = bf16_bits(li);
-                const float sr = sl[2 * lane][cc], si = sl[2 * lane + 1][cc];
-                if (long_pole) {
-                    const double nr = t.x * y.x - t.y * y.y + (double)sr;
-                    const double ni = t.x * y.y + t.y * y.x + (double)si;
-                    y = make_double2(nr, ni);
-                } else {
-                    const float tr = (float)t.x, ti = (float)t.y;
-                    const float nr = fmaf(tr, yr, fmaf(-ti, yi, sr));
-                    const float ni = fmaf(tr, yi, fmaf(ti, yr, si));
-                    y = make_double2((double)nr, (double)ni);
-                }
-            }
-        }
+        const int valid_cols = min(kChunk, nb - c0);
+        if (long_pole)
+            carry_chunk<double>(sl, tot64, f, q, valid_cols, A64, y64, yh, yl, row_len2, c0);
+        else
+            carry_chunk<float>(sl, tot32, f, q, valid_cols, A32, y32, yh, yl, row_len2, c0);
         __syncthreads();
     }
-    if (lane < 16) state[(int64_t)det * n_fpad + gf] = y;
+    if (q == 0)
+        state[(int64_t)det * n_fpad + gf] =
+            long_pole ? make_double2(y64.r, y64.i) : make_double2((double)y32.r, (double)y32.i);
     (void)nb_max;
 }
 
-// One workgroup of (2L/64) waves per (template, 64 columns); a column is
-// (detector, block).  Wave w computes output rows [64w, 64w+64) x the 64 columns.
+// Output product, one workgroup of (2L/64) waves per (template, 128 columns); a
+// column is (detector, block).  Wave w computes output rows [64w, 64w+64) x the
+// 128 columns: 2 x 4 accumulator tiles of 32x32.  Per K step of 16 the B operand
+// (128 columns x 16 entries, hi and lo) is staged once into LDS for all waves
+// (double-buffered; 48-byte column pitch so the 16-byte fragment reads of 16
+// lanes cover the 64 banks once), while each wave streams its own A fragments
+// from global memory, prefetching the next step's during the current MFMAs.
+// Workgroups are dispatched round-robin over the XCDs (id % kXcds); the mapping
+// gives every column tile of a template to the same XCD, one after the other, so
+// the template's operand is fetched into that XCD's L2 once.
+constexpr int kXcds = 8;
+constexpr int kOutCols = 128;
+constexpr int kBPitch = 24;   // bf16 per staged column per plane (16 used + 8 pad)
+
 __global__ __launch_bounds__(512) void block_output_kernel(
     const BTemplate *__restrict__ tmpls, const uint16_t *__restrict__ pa,
     const uint16_t *__restrict__ yt, int64_t y_per_det, const uint16_t *__restrict__ xs,
     int64_t xs_stride, int32_t hist_pad, int32_t n_det, int32_t L, int32_t nb, int32_t n,
-    int32_t n_templates, float *__restrict__ z) {
-    const int t = blockIdx.x;
+    int32_t n_templates, float *__restrict__ z, int32_t n_col_tiles) {
+    __shared__ __attribute__((aligned(16))) uint16_t bs[2][2][kOutCols * kBPitch];
+    const int wg = blockIdx.x;
+    const int xcd = wg % kXcds;
+    const int seq = wg / kXcds;
+    const int t = (seq / n_col_tiles) * kXcds + xcd;
+    const int col_tile = seq % n_col_tiles;
+    if (t >= n_templates) return;
     const BTemplate bt = tmpls[t];
-    const int wave = threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    const int rt_per = (2 * L) / 32;             // row tiles of the template
+    const int nthreads = blockDim.x;
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int lane = tid % kWave;
+    const int rt_per = (2 * L) / 32;
     const int kg = (lane / 32) * 8;
     const int ncols = n_det * nb;
-    int det[2], blk[2];
-    bool valid[2];
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-        const int c = blockIdx.y * 64 + ct * 32 + (lane % 32);
-        valid[ct] = c < ncols;
-        const int cc = valid[ct] ? c : 0;
-        det[ct] = cc / nb;
-        blk[ct] = cc % nb;
-    }
-    f32x16 acc[2][2] = {};
     const int64_t row_len = 2 * (int64_t)bt.fpad;
-    // state part: K = 2*fpad state entries
-    for (int ks = 0; ks < bt.nks_p; ++ks) {
-        bf16x8 ah[2], al[2], bh[2], bl[2];
+    const int nks = bt.nks_p + bt.nks_m;
+
+    // global source of the staged B entries of step ks for column c (8 entries, one plane)
+    auto b_src = [&](int ks, int c, int plane, int half) -> const uint16_t * {
+        const int cc = min(col_tile * kOutCols + c, ncols - 1);
+        const int det = cc / nb, blk = cc % nb;
+        if (ks < bt.nks_p)
+            return yt + (int64_t)plane * n_det * y_per_det + (int64_t)det * y_per_det + bt.y_off +
+                   (int64_t)blk * row_len + 16 * ks + 8 * half;
+        return xs + (int64_t)plane * n_det * xs_stride + (int64_t)det * xs_stride + hist_pad +
+               (int64_t)blk * L + bt.sigma_lo + 16 * (ks - bt.nks_p) + 8 * half;
+    };
+    const int n_b_items = kOutCols * 2 * 2;   // (column, plane, half) 16-byte items per step
+    auto stage = [&](int ks, int buf) {
+        for (int e = tid; e < n_b_items; e += nthreads) {
+            const int c = e >> 2, plane = (e >> 1) & 1, half = e & 1;
+            const bf16x8 v = load8(b_src(ks, c, plane, half));
+            *reinterpret_cast<bf16x8 *>(&bs[buf][plane][c * kBPitch + 8 * half]) = v;
+        }
+    };
+    auto a_ptr = [&](int ks, int r) -> const uint16_t * {
+        return pa + bt.a_off + ((int64_t)ks * rt_per + 2 * wave + r) * 1024 + (lane % 32) * 16 + kg;
+    };
+
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f32x16{};
+
+    bf16x8 ah[2], al[2];
+    if (nks > 0) {
+        stage(0, 0);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-            const uint16_t *p = pa + bt.a_off +
-                                ((int64_t)ks * rt_per + 2 * wave + r) * 1024 + (lane % 32) * 16 + kg;
-            ah[r] = load8(p);
-            al[r] = load8(p + 512);
+            ah[r] = load8(a_ptr(0, r));
+            al[r] = load8(a_ptr(0, r) + 512);
         }
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            const uint16_t *q = yt + (int64_t)det[ct] * y_per_det + bt.y_off +
-                                (int64_t)blk[ct] * row_len + 16 * ks + kg;
-            bh[ct] = load8(q);
-            bl[ct] = load8(q + (int64_t)n_det * y_per_det);
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) acc[r][ct] = mma3(ah[r], al[r], bh[ct], bl[ct], acc[r][ct]);
     }
-    // input part: K = offsets sigma in [sigma_lo, L)
-    for (int ks = 0; ks < bt.nks_m; ++ks) {
-        bf16x8 ah[2], al[2], bh[2], bl[2];
+    __syncthreads();
+    for (int ks = 0; ks < nks; ++ks) {
+        const int buf = ks & 1;
+        // prefetch the next step: A into registers, B into the other LDS buffer
+        bf16x8 nh[2], nl[2];
+        const bool more = ks + 1 < nks;
+        if (more) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const uint16_t *p = pa + bt.a_off +
-                                ((int64_t)(bt.nks_p + ks) * rt_per + 2 * wave + r) * 1024 +
-                                (lane % 32) * 16 + kg;
-            ah[r] = load8(p);
-            al[r] = load8(p + 512);
+            for (int r = 0; r < 2; ++r) {
+                nh[r] = load8(a_ptr(ks + 1, r));
+                nl[r] = load8(a_ptr(ks + 1, r) + 512);
+            }
+            stage(ks + 1, buf ^ 1);
         }
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            const uint16_t *q = xs + (int64_t)det[ct] * xs_stride + hist_pad +
-                                (int64_t)blk[ct] * L + bt.sigma_lo + 16 * ks + kg;
-            bh[ct] = load8(q);
-            bl[ct] = load8(q + (int64_t)n_det * xs_stride);
+        for (int ct = 0; ct < 4; ++ct) {
+            const int c = ct * 32 + (lane % 32);
+            const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&bs[buf][0][c * kBPitch + kg]);
+            const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&bs[buf][1][c * kBPitch + kg]);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) acc[r][ct] = mma3(ah[r], al[r], bh, bl, acc[r][ct]);
         }
+        if (more) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) acc[r][ct] = mma3(ah[r], al[r], bh[ct], bl[ct], acc[r][ct]);
+            for (int r = 0; r < 2; ++r) {
+                ah[r] = nh[r];
+                al[r] = nl[r];
+            }
+        }
+        __syncthreads();   // buffer `buf` free, buffer `buf^1` complete
     }
     // rows (2j + re/im): accumulator entries 4q..4q+3 are (j0 re, j0 im, j0+1 re, j0+1 im)
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-        if (!valid[ct]) continue;
-        float *zr = z + 2 * (((int64_t)det[ct] * n_templates + t) * n + (int64_t)blk[ct] * L);
+    for (int ct = 0; ct < 4; ++ct) {
+        const int c = col_tile * kOutCols + ct * 32 + (lane % 32);
+        if (c >= ncols) continue;
+        const int det = c / nb, blk = c % nb;
+        float *zr = z + 2 * (((int64_t)det * n_templates + t) * n + (int64_t)blk * L);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = 64 * wave + 32 * r + 8 * q + 4 * (lane / 32);
                 const int j0 = row / 2;
-                float4 v = make_float4(acc[r][ct][4 * q], acc[r][ct][4 * q + 1],
-                                       acc[r][ct][4 * q + 2], acc[r][ct][4 * q + 3]);
+                const float4 v = make_float4(acc[r][ct][4 * q], acc[r][ct][4 * q + 1],
+                                             acc[r][ct][4 * q + 2], acc[r][ct][4 * q + 3]);
                 *reinterpret_cast<float4 *>(zr + 2 * j0) = v;
             }
         }
@@ -257,10 +372,12 @@ hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *
                            bk.n_det, L, nb, bk.max_chunk / L, bk.d_aL, bk.d_lp, bk.d_state64,
                            bk.n_fpad, bk.d_yt, bk.y_per_det);
     const int ncols = bk.n_det * nb;
-    const dim3 grid(bk.n_templates, (ncols + 63) / 64);
+    const int col_tiles = (ncols + kOutCols - 1) / kOutCols;
+    const int64_t groups = (bk.n_templates + kXcds - 1) / kXcds;
+    const dim3 grid((unsigned)(groups * kXcds * col_tiles));
     hipLaunchKernelGGL(block_output_kernel, grid, dim3((2 * L / 64) * kWave), 0, s, bk.d_btmpl,
                        bk.d_pa, bk.d_yt, bk.y_per_det, bk.d_xs, bk.xs_stride, bk.hist_pad, bk.n_det,
-                       L, nb, n, bk.n_templates, reinterpret_cast<float *>(z));
+                       L, nb, n, bk.n_templates, reinterpret_cast<float *>(z), col_tiles);
     return hipGetLastError();
 }
 
