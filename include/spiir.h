@@ -153,6 +153,32 @@ spiir_status spiir_peaks(const float *z, int64_t rows, int32_t n, int32_t window
                          int32_t *argmax, void *stream);
 
 /*
+ * ---- Trigger selection (Section II.C.1) ----
+ * E|z_t|^2 for stationary white input of unit variance (the whitened strain of
+ * Section II.A), per template, in FP64 on the host from the bank's coefficients:
+ *   E|z_t|^2 = sum_{k,l in t} Re[ b_k conj(b_l) conj(a_l)^(d_k-d_l) / (1 - a_k conj(a_l)) ]
+ * (pairs ordered so that d_k >= d_l).  power: host double [T].  Synchronous.
+ */
+spiir_status spiir_bank_noise_power(const spiir_bank *bank, double *power);
+
+/*
+ * Single-detector candidates of Section II.C.1: at every sample the template with
+ * the largest normalised SNR^2  rho2_t = |z_t|^2 * weight_t  (|z|^2 = re*re + im*im,
+ * every product and sum rounded to float32; weight_t = 2 / E|z_t|^2 normalises each
+ * quadrature to unit variance) is a candidate when rho2 > threshold^2; a template
+ * keeps at most one candidate per window of `window` samples, the largest (lowest
+ * sample on ties; lowest template on ties across templates).
+ *   z        device complex64 [n_det][n_templates][n]
+ *   weight   device float32 [n_templates]
+ *   work     device uint64 [n_det][n_templates][W], W = ceil(n/window): scratch
+ *   snr      device float32 [n_det][n_templates][W]: sqrtf(rho2) of the kept candidate, 0 if none
+ *   index    device int32   [n_det][n_templates][W]: its sample in [0, n), -1 if none
+ */
+spiir_status spiir_triggers(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                            const float *weight, float threshold, int32_t window, void *work,
+                            float *snr, int32_t *index, void *stream);
+
+/*
  * ---- Differentiation (FP32 scan mode only) ----
  * For fitting coefficients to a target response (the overlap of Eq. overlap,
  * Section II.B.1, between a template and the summed filter response).  These

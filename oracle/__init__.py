@@ -63,6 +63,8 @@ def _load():
         lib.spo_overlap_grad.argtypes = [_I32, _P, _P, _P, _P, _I64, _P, _I32, _F64, _P, _P, _P]
         for f in (lib.spo_filter, lib.spo_peaks, lib.spo_grad, lib.spo_overlap_grad):
             f.restype = ctypes.c_int
+        lib.spo_noise_power.argtypes = [_I32, _P, _P, _P, _P, _P]
+        lib.spo_noise_power.restype = ctypes.c_int
         lib.spo_threads.argtypes = []
         lib.spo_threads.restype = ctypes.c_int
         _lib = lib
@@ -207,6 +209,50 @@ def overlap_grad(bank, target: np.ndarray, mode: int = 0, scale: Optional[float]
                                   _ptr(gb))
     _check(rc, "overlap_grad")
     return ov, ga, gb
+
+
+def noise_power(bank) -> np.ndarray:
+    """E|z_t|^2 for unit-variance white input (closed form, FP64), per template."""
+    offsets, a, b, d = _bank_arrays(bank)
+    out = np.empty(bank.n_templates, dtype=np.float64)
+    rc = _load().spo_noise_power(bank.n_templates, _ptr(offsets), _ptr(a), _ptr(b), _ptr(d), _ptr(out))
+    _check(rc, "noise_power")
+    return out
+
+
+def triggers(z: np.ndarray, weight: np.ndarray, threshold: float, window: int):
+    """Trigger selection of Section II.C.1 on z[D][T][n] (complex64), decided in float32.
+
+    rho2_t[n] = (re*re + im*im) * weight_t, each product and the sum rounded to
+    float32 (weight_t = 2 / E|z_t|^2 normalises each quadrature to unit variance).
+    For each sample the template with the largest rho2 (lowest index on ties) is a
+    candidate if rho2 > threshold^2; per template and window of ``window`` samples the
+    candidate with the largest rho2 (lowest sample on ties) is kept.  Returns
+    (snr[D][T][W] float32, 0 where none; index[D][T][W] int32 sample in the packet,
+    -1 where none), snr = sqrt(rho2) in float32.
+    """
+    z = np.ascontiguousarray(z, dtype=np.complex64)
+    D, T, n = z.shape
+    W = (n + window - 1) // window
+    re = z.real.astype(np.float32)
+    im = z.imag.astype(np.float32)
+    w = np.asarray(weight, dtype=np.float32)
+    p = ((re * re).astype(np.float32) + (im * im).astype(np.float32)).astype(np.float32)
+    r2 = (p * w[None, :, None]).astype(np.float32)
+    thr2 = np.float32(threshold) * np.float32(threshold)
+    snr = np.zeros((D, T, W), dtype=np.float32)
+    idx = np.full((D, T, W), -1, dtype=np.int32)
+    for det in range(D):
+        tstar = np.argmax(r2[det], axis=0)               # lowest template on ties
+        best = r2[det][tstar, np.arange(n)]
+        for i in np.nonzero(best > thr2)[0]:
+            t, wdx = int(tstar[i]), int(i) // window
+            if best[i] > (snr[det, t, wdx] if idx[det, t, wdx] >= 0 else np.float32(-1)):
+                snr[det, t, wdx] = best[i]
+                idx[det, t, wdx] = int(i)
+    got = idx >= 0
+    snr[got] = np.sqrt(snr[got]).astype(np.float32)
+    return snr, idx
 
 
 def threads() -> int:

@@ -353,3 +353,58 @@ int spo_overlap_grad(int32_t n_templates, const int32_t *offsets, const double *
     }
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Noise power and trigger selection (Section II.C.1).                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * E|z_t[n]|^2 for stationary white input of unit variance: with
+ * z_t[n] = sum_k sum_m b_k a_k^m x[n-d_k-m],
+ *   E|z_t|^2 = sum_{k,l} b_k conj(b_l) sum_{m,m' : d_k+m = d_l+m'} a_k^m conj(a_l)^{m'}
+ *            = sum_{k,l} b_k conj(b_l) conj(a_l)^(d_k-d_l) / (1 - a_k conj(a_l))   (d_k >= d_l)
+ * and the conjugate of the (l,k) term when d_k < d_l.  power[T] (real).
+ */
+int spo_noise_power(int32_t n_templates, const int32_t *offsets, const double *a, const double *b,
+                    const int32_t *d, double *power)
+{
+    if (n_templates < 0)
+        return SPO_EINVAL;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t t = 0; t < n_templates; ++t) {
+        double acc = 0.0;
+        for (int64_t k = offsets[t]; k < offsets[t + 1]; ++k) {
+            for (int64_t l = offsets[t]; l < offsets[t + 1]; ++l) {
+                /* term(k,l) = b_k conj(b_l) conj(a_l)^(d_k-d_l) / (1 - a_k conj(a_l)) for d_k >= d_l;
+                   only the real part of the double sum survives (it is Hermitian) */
+                int64_t p = k, q = l;
+                if (d[k] < d[l]) { p = l; q = k; }   /* conj(term(l,k)) has the same real part */
+                const double apr = a[2 * p], api = a[2 * p + 1];
+                const double aqr = a[2 * q], aqi = -a[2 * q + 1];          /* conj(a_q) */
+                /* num = b_p conj(b_q) conj(a_q)^(d_p - d_q), the power by repeated squaring */
+                double nr = b[2 * p] * b[2 * q] + b[2 * p + 1] * b[2 * q + 1];
+                double ni = b[2 * p + 1] * b[2 * q] - b[2 * p] * b[2 * q + 1];
+                double sr = aqr, si = aqi;
+                for (int32_t e = d[p] - d[q]; e > 0; e >>= 1) {
+                    if (e & 1) {
+                        const double tr = nr * sr - ni * si;
+                        const double ti = nr * si + ni * sr;
+                        nr = tr;
+                        ni = ti;
+                    }
+                    const double qr = sr * sr - si * si;
+                    const double qi = 2.0 * sr * si;
+                    sr = qr;
+                    si = qi;
+                }
+                /* den = 1 - a_p conj(a_q) */
+                const double dr = 1.0 - (apr * aqr - api * aqi);
+                const double di = -(apr * aqi + api * aqr);
+                const double den2 = dr * dr + di * di;
+                acc += (nr * dr + ni * di) / den2;   /* Re(num / den) */
+            }
+        }
+        power[t] = acc;
+    }
+    return SPO_OK;
+}

@@ -1,6 +1,9 @@
 // C-ABI of libspiir: argument validation, bank layout planning and launches.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <complex>
+#include <thread>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -305,6 +308,12 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         bk.time_tile = time_tile > 0 ? time_tile : 0;
         bk.block_len = block_len;
         bk.ckpt_stride = ckpt_stride;
+        bk.h_offsets.assign(offsets, offsets + n_templates + 1);
+        if (F > 0) {
+            bk.h_a.assign(a, a + 2 * F);
+            bk.h_b.assign(b, b + 2 * F);
+            bk.h_delay.assign(delay, delay + F);
+        }
         bk.long_pole = opts.long_pole_abs_a > 0 ? opts.long_pole_abs_a : 0.999;
         int32_t tile = spiir::kWindowFloats - hist_len - spiir::kSub;
         tile = std::min(tile, bk.max_chunk);
@@ -481,6 +490,60 @@ spiir_status spiir_filter_chunk(spiir_bank *h, const float *x, int32_t n, float 
     }
     SPIIR_HIP(spiir::launch_hist_update(bk, x, n, s));
     SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), peak, argmax, s));
+    return SPIIR_OK;
+}
+
+spiir_status spiir_bank_noise_power(const spiir_bank *h, double *power) {
+    if (h == nullptr || power == nullptr) return fail(SPIIR_E_INVAL, "bank or power is NULL");
+    const spiir::Bank &bk = h->bk;
+    const int32_t T = bk.n_templates;
+    auto work = [&](int32_t t0, int32_t t1) {
+        for (int32_t t = t0; t < t1; ++t) {
+            double acc = 0.0;
+            const int32_t lo = bk.h_offsets[t], hi = bk.h_offsets[t + 1];
+            for (int32_t k = lo; k < hi; ++k)
+                for (int32_t l = lo; l < hi; ++l) {
+                    const int32_t p = bk.h_delay[k] >= bk.h_delay[l] ? k : l;
+                    const int32_t q = p == k ? l : k;
+                    const std::complex<double> ap(bk.h_a[2 * p], bk.h_a[2 * p + 1]);
+                    const std::complex<double> aq(bk.h_a[2 * q], -bk.h_a[2 * q + 1]);   // conj(a_q)
+                    const std::complex<double> bp(bk.h_b[2 * p], bk.h_b[2 * p + 1]);
+                    const std::complex<double> bq(bk.h_b[2 * q], -bk.h_b[2 * q + 1]);   // conj(b_q)
+                    std::complex<double> pw(1.0, 0.0), base = aq;
+                    for (int32_t e = bk.h_delay[p] - bk.h_delay[q]; e > 0; e >>= 1) {
+                        if (e & 1) pw *= base;
+                        base *= base;
+                    }
+                    acc += (bp * bq * pw / (1.0 - ap * aq)).real();
+                }
+            power[t] = acc;
+        }
+    };
+    const int32_t nt = (int32_t)std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 64u));
+    std::vector<std::thread> pool;
+    std::atomic<int32_t> next{0};
+    for (int32_t w = 0; w < nt; ++w)
+        pool.emplace_back([&]() {
+            for (int32_t t; (t = next.fetch_add(1)) < T;) work(t, t + 1);
+        });
+    for (auto &th : pool) th.join();
+    return SPIIR_OK;
+}
+
+spiir_status spiir_triggers(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                            const float *weight, float threshold, int32_t window, void *work,
+                            float *snr, int32_t *index, void *stream) {
+    if (n_det < 0 || n_templates < 0 || n < 0) return fail(SPIIR_E_INVAL, "sizes must be >= 0");
+    if (window < 1) return fail(SPIIR_E_INVAL, "window must be >= 1");
+    if (!std::isfinite(threshold) || threshold < 0.0f)
+        return fail(SPIIR_E_INVAL, "threshold must be finite and >= 0");
+    if ((int64_t)n_det * n_templates * n == 0) return SPIIR_OK;
+    if (z == nullptr || weight == nullptr || work == nullptr || snr == nullptr || index == nullptr)
+        return fail(SPIIR_E_INVAL, "z, weight, work, snr and index must be non-NULL");
+    SPIIR_HIP(spiir::launch_triggers(reinterpret_cast<const float2 *>(z), n_det, n_templates, n,
+                                     weight, threshold, window,
+                                     static_cast<unsigned long long *>(work), snr, index,
+                                     static_cast<hipStream_t>(stream)));
     return SPIIR_OK;
 }
 

@@ -110,6 +110,10 @@ struct Bank {
     int64_t device_bytes = 0;
     hipStream_t last_stream = nullptr;
 
+    // host copy of the bank (noise power on request)
+    std::vector<int32_t> h_offsets, h_delay;
+    std::vector<float> h_a, h_b;
+
     // optional kernel timing
     std::vector<hipEvent_t> ev_start, ev_stop;
     int64_t timed = 0;
@@ -133,6 +137,9 @@ hipError_t launch_reduce_peaks(const Bank &bk, int32_t n, float2 *z, float *peak
 hipError_t launch_peaks(const float2 *z, int64_t rows, int32_t n, int32_t window, float *peak,
                         int32_t *argmax, hipStream_t s);
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t s);
+hipError_t launch_triggers(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
+                           const float *weight, float threshold, int32_t window,
+                           unsigned long long *work, float *snr, int32_t *index, hipStream_t s);
 hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *z, hipStream_t s);
 spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const float *b,
                         const int32_t *delay, hipStream_t s, std::string &err);

@@ -7,6 +7,7 @@
 // every product and the sum rounded to float32 (no contraction) so that the
 // decision is reproducible; among equal |z|^2 the lowest index wins.  The
 // block-wide arg-max reduction uses wave shuffles and one LDS exchange.
+#include <algorithm>
 #include <climits>
 
 #include "internal.h"
@@ -129,6 +130,56 @@ __global__ __launch_bounds__(kHistThreads) void hist_update_kernel(float *__rest
     }
 }
 
+// Trigger selection (Section II.C.1).  Pass 1: one thread per (detector, sample)
+// finds the template with the largest normalised SNR^2 (lowest template on ties)
+// and, above threshold, offers it to that template's window slot with a 64-bit
+// atomic max of (rho2 bits << 32 | ~sample): the largest rho2 wins, then the lowest
+// sample, whatever the order of the offers.  Pass 2 decodes the slots.
+__global__ void trigger_keys_kernel(const float2 *__restrict__ z, int32_t n_templates, int32_t n,
+                                    const float *__restrict__ weight, float thr2, int32_t window,
+                                    int32_t n_win, unsigned long long *__restrict__ keys) {
+    const int det = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 *zd = z + (int64_t)det * n_templates * n + i;
+    float best = -1.0f;
+    int bt = -1;
+    for (int t = 0; t < n_templates; ++t) {
+        const float2 v = zd[(int64_t)t * n];
+        const float r2 = __fmul_rn(abs2_rn(v.x, v.y), weight[t]);
+        if (r2 > best) {
+            best = r2;
+            bt = t;
+        }
+    }
+    if (bt >= 0 && best > thr2) {
+        const unsigned long long key =
+            ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+        atomicMax(keys + ((int64_t)det * n_templates + bt) * n_win + i / window, key);
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t count) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = 0ull;
+}
+
+__global__ void trigger_decode_kernel(const unsigned long long *__restrict__ keys, int64_t count,
+                                      float *__restrict__ snr, int32_t *__restrict__ index) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long key = keys[k];
+        if (key == 0ull) {
+            snr[k] = 0.0f;
+            index[k] = -1;
+        } else {
+            snr[k] = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+            index[k] = (int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+        }
+    }
+}
+
 __global__ void zero_kernel(float4 *__restrict__ p, int64_t n4) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -167,6 +218,23 @@ hipError_t launch_hist_update(const Bank &bk, const float *x, int32_t n, hipStre
     if (n <= 0 || bk.hist_len == 0) return hipSuccess;
     hipLaunchKernelGGL(hist_update_kernel, dim3(bk.n_det), dim3(kHistThreads), 0, s, bk.d_hist,
                        bk.hist_len, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_triggers(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
+                           const float *weight, float threshold, int32_t window,
+                           unsigned long long *work, float *snr, int32_t *index, hipStream_t s) {
+    const int32_t n_win = (n + window - 1) / window;
+    const int64_t count = (int64_t)n_det * n_templates * n_win;
+    if (count == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    // clear the slots with a kernel (graph-safe)
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, work, count);
+    const float thr2 = threshold * threshold;
+    hipLaunchKernelGGL(trigger_keys_kernel, dim3((n + 255) / 256, n_det), dim3(256), 0, s, z,
+                       n_templates, n, weight, thr2, window, n_win, work);
+    hipLaunchKernelGGL(trigger_decode_kernel, dim3((unsigned)blocks), dim3(256), 0, s, work, count,
+                       snr, index);
     return hipGetLastError();
 }
 

@@ -65,12 +65,9 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, float2 *
                                          const float (&br)[MAXM], const float (&bi)[MAXM],
                                          const int (&base)[MAXM], float (&yr)[MAXM],
                                          float (&yi)[MAXM], float2 *__restrict__ out) {
-    float accr[kSub], acci[kSub];
+    float2 acc[kSub];
 #pragma unroll
-    for (int s = 0; s < kSub; ++s) {
-        accr[s] = 0.0f;
-        acci[s] = 0.0f;
-    }
+    for (int s = 0; s < kSub; ++s) acc[s] = make_float2(0.0f, 0.0f);
 #pragma unroll
     for (int j = 0; j < MAXM; ++j) {
         if (j < m) {  // wave-uniform
@@ -84,8 +81,8 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, float2 *
                     const float ni = fmaf(ar[j], im, fmaf(ai[j], r, bi[j] * xv));
                     r = nr;
                     im = ni;
-                    accr[s] += r;
-                    acci[s] += im;
+                    acc[s].x += r;
+                    acc[s].y += im;
                 }
             }
             yr[j] = r;
@@ -94,7 +91,7 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, float2 *
     }
     // lane -> sample transpose: row `lane` holds this lane's kSub partial sums
 #pragma unroll
-    for (int s = 0; s < kSub; ++s) red[lane * kRedStride + s] = make_float2(accr[s], acci[s]);
+    for (int s = 0; s < kSub; ++s) red[lane * kRedStride + s] = acc[s];
     lds_fence();
     const int q = lane >> 4;     // quarter of the wave: rows 16q .. 16q+15
     const int s = lane & 15;     // sample of the sub-tile this lane reduces
@@ -122,13 +119,17 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     int32_t win_floats, float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg) {
     extern __shared__ float smem[];
     float *win = smem;
-    const int wave = threadIdx.x / kWave;
+    // wave-uniform values live in scalar registers (readfirstlane), so that the
+    // per-slot tests below are scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     float2 *red = reinterpret_cast<float2 *>(smem + win_floats) + wave * kWave * kRedStride;
     const int det = blockIdx.y;
     const int sidx = blockIdx.x * kScanWaves + wave;
     const bool active = sidx < n_slices;
-    const Slice sl = active ? slices[sidx] : Slice{0, 0, 0, 0};
+    Slice sl = active ? slices[sidx] : Slice{0, 0, 0, 0};
+    sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
+    sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
     const int m = sl.n_slots;
 
     float ar[MAXM], ai[MAXM], br[MAXM], bi[MAXM], yr[MAXM], yi[MAXM];
@@ -247,13 +248,15 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
         if (lane == 0)
             item = __hip_atomic_fetch_add(&queue->head, 1u, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
-        item = __shfl(item, 0);
+        item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total) break;
         const uint32_t tau = item / per_round;
-        const int code = order[item % per_round];
+        const int code = __builtin_amdgcn_readfirstlane(order[item % per_round]);
         const int det = code / n_slices;
         const int sidx = code % n_slices;
-        const Slice sl = slices[sidx];
+        Slice sl = slices[sidx];
+        sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
+        sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
         const int m = sl.n_slots;
         const int n0 = (int)tau * tile;
         const int T = min(tile, n - n0);

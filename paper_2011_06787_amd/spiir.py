@@ -30,7 +30,7 @@ EXPORTS = (
     "spiir_opts_default", "spiir_bank_create", "spiir_bank_destroy", "spiir_bank_reset",
     "spiir_bank_get_info", "spiir_filter_chunk", "spiir_peaks", "spiir_last_error",
     "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count", "spiir_forward",
-    "spiir_backward", "spiir_bank_set_coeffs",
+    "spiir_backward", "spiir_bank_set_coeffs", "spiir_bank_noise_power", "spiir_triggers",
 )
 
 
@@ -97,12 +97,16 @@ def load():
     lib.spiir_forward.argtypes = [_P, _P, ctypes.c_int32, _P, _P, _P]
     lib.spiir_backward.argtypes = [_P, _P, ctypes.c_int32, _P, _P, _P, _P, _P]
     lib.spiir_bank_set_coeffs.argtypes = [_P, _P, _P, _P]
+    lib.spiir_bank_noise_power.argtypes = [_P, _P]
+    lib.spiir_triggers.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                   ctypes.c_float, ctypes.c_int32, _P, _P, _P, _P]
     lib.spiir_last_error.argtypes = []
     lib.spiir_last_error.restype = ctypes.c_char_p
     for name in ("spiir_bank_create", "spiir_bank_destroy", "spiir_bank_reset",
                  "spiir_bank_get_info", "spiir_filter_chunk", "spiir_peaks",
                  "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count",
-                 "spiir_forward", "spiir_backward", "spiir_bank_set_coeffs"):
+                 "spiir_forward", "spiir_backward", "spiir_bank_set_coeffs",
+                 "spiir_bank_noise_power", "spiir_triggers"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -258,6 +262,12 @@ class SpiirBank:
         _check("spiir_bank_set_coeffs", load().spiir_bank_set_coeffs(
             self._h, a.data_ptr(), b.data_ptr(), _stream_ptr(stream)))
 
+    def noise_power(self) -> np.ndarray:
+        """E|z_t|^2 per template for unit-variance white input (FP64, host)."""
+        out = np.empty(self.n_templates, dtype=np.float64)
+        _check("spiir_bank_noise_power", load().spiir_bank_noise_power(self._h, out.ctypes.data))
+        return out
+
     def set_timing(self, enable: bool, capacity: int = 4096):
         """Bracket the main filtering kernel with HIP events (see spiir.h)."""
         _check("spiir_bank_set_timing",
@@ -345,3 +355,22 @@ def spiir_filter(a, b, x, bank: SpiirBank):
     if _autograd_fn is None:
         _autograd_fn = _make_autograd()
     return _autograd_fn.apply(a, b, x, bank)
+
+
+def triggers(z, weight, threshold: float = 4.0, window: int = 2048, work=None, stream=None):
+    """Single-detector candidates (Sec. II.C.1) from z (cuda complex64 [D][T][n]).
+
+    ``weight`` cuda float32 [T] (2 / E|z_t|^2).  Returns (snr, index), each [D][T][W].
+    """
+    import torch
+    assert z.is_cuda and z.dtype == torch.complex64 and z.is_contiguous() and z.dim() == 3
+    D, T, n = (int(v) for v in z.shape)
+    W = (n + window - 1) // window
+    if work is None:
+        work = torch.empty((D, T, W), dtype=torch.int64, device=z.device)
+    snr = torch.empty((D, T, W), dtype=torch.float32, device=z.device)
+    idx = torch.empty((D, T, W), dtype=torch.int32, device=z.device)
+    _check("spiir_triggers", load().spiir_triggers(z.data_ptr(), D, T, n, weight.data_ptr(),
+                                                   float(threshold), int(window), work.data_ptr(),
+                                                   snr.data_ptr(), idx.data_ptr(), _stream_ptr(stream)))
+    return snr, idx

@@ -1,0 +1,59 @@
+"""Trigger selection (Section II.C.1) on the GPU: normalised SNR, loudest template per
+sample above threshold, one candidate per template per window."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("D, T, n, window", [(1, 7, 1000, 256), (3, 40, 2048, 2048), (2, 3, 100, 7)])
+def test_triggers_bit_exact_on_seeded_series(gpu, D, T, n, window):
+    import torch
+    rng = np.random.default_rng(D * 100 + T)
+    z = ((rng.standard_normal((D, T, n)) + 1j * rng.standard_normal((D, T, n))) * 1.7).astype(np.complex64)
+    z[0, 1, 5] = z[0, 2, 5] = 11 + 11j           # tie across templates
+    w = rng.uniform(0.4, 1.6, size=T).astype(np.float32)
+    snr, idx = gpu.triggers(torch.from_numpy(z).cuda(), torch.from_numpy(w).cuda(), 4.0, window)
+    snr_ref, idx_ref = oracle.triggers(z, w, 4.0, window)
+    assert np.array_equal(idx.cpu().numpy(), idx_ref)
+    assert np.array_equal(snr.cpu().numpy(), snr_ref)
+    assert (idx_ref >= 0).sum() > 0
+
+
+def test_noise_power_matches_oracle(gpu):
+    w = synth.tiny()
+    rng = np.random.default_rng(5)
+    bank = synth.draw_filters(rng, np.array([30, 1, 200, 64]))
+    for bk in (w.bank, bank):
+        with gpu.SpiirBank.from_bank(bk, max_chunk=256) as sb:
+            p = sb.noise_power()
+        assert np.allclose(p, oracle.noise_power(bk), rtol=1e-10, atol=0)
+
+
+def test_triggers_end_to_end_on_noise(gpu):
+    """Normalised SNR of the filtered noise has unit variance per quadrature (so
+    E rho^2 = 2), and every trigger is consistent with the series it came from."""
+    import torch
+    w = synth.realistic(n_templates=64, seconds=8)
+    with gpu.SpiirBank.from_bank(w.bank, max_chunk=2048) as sb:
+        power = sb.noise_power()
+        weight = torch.from_numpy((2.0 / power).astype(np.float32)).cuda()
+        x = torch.from_numpy(w.input()).cuda()
+        zs = []
+        for i in range(8):
+            z, _, _ = sb.filter_chunk(x[:, i * 2048:(i + 1) * 2048].contiguous(), want_peaks=False)
+            zs.append(z.clone())
+        z = torch.cat(zs, dim=-1)
+        snr, idx = gpu.triggers(z, weight, 4.0, 2048)
+    zc = z.cpu().numpy()
+    rho2 = np.abs(zc[:, :, 4096:]) ** 2 * (2.0 / power)[None, :, None]   # after 2 s of warm-up
+    assert abs(rho2.mean() / 2.0 - 1.0) < 0.1
+    snr, idx = snr.cpu().numpy(), idx.cpu().numpy()
+    d, t, k = np.nonzero(idx >= 0)
+    assert len(d) > 0
+    vals = np.abs(zc[d, t, k * 2048 + idx[d, t, k]]) * np.sqrt(2.0 / power[t])
+    assert np.allclose(snr[d, t, k], vals, rtol=1e-5)
+    assert np.all(snr[d, t, k] > 4.0)

@@ -385,3 +385,67 @@ def test_empty_inputs():
     assert z.shape == (1, 3, 0)
     z = oracle.filter(bank, np.ones(5))
     assert np.all(z[0, 1] == 0)   # a template with no filters outputs zero
+
+
+def test_noise_power_single_filter_textbook():
+    # one filter: E|y|^2 = |b|^2 / (1 - |a|^2) for unit white input
+    bank = small_bank(40, [1], max_delay=100, tau=(0.01, 4.0))
+    a = complex(bank.a[0]); b = complex(bank.b[0])
+    assert oracle.noise_power(bank)[0] == pytest.approx(abs(b) ** 2 / (1 - abs(a) ** 2), rel=1e-12)
+
+
+def test_noise_power_equals_impulse_energy():
+    # Parseval for white input: E|z_t|^2 = sum_m |u_t[m]|^2 (impulse response energy)
+    bank = small_bank(41, [7, 3, 12], max_delay=200, tau=(0.002, 0.05))
+    n = 6000      # |a|^n < 1e-30 for tau <= 0.05 s
+    u = oracle.filter(bank, synth.impulse(n))[0]
+    energy = np.sum(np.abs(u) ** 2, axis=-1)
+    assert np.allclose(oracle.noise_power(bank), energy, rtol=1e-10)
+
+
+def test_noise_power_monte_carlo():
+    bank = small_bank(42, [6], max_delay=40, tau=(0.002, 0.004))
+    x = np.random.default_rng(43).standard_normal(300_000)
+    z = oracle.filter(bank, x)[0, 0][500:]
+    n_eff = len(z) * (1 - np.abs(bank.a.astype(complex)).max())
+    assert abs(np.mean(np.abs(z) ** 2) / oracle.noise_power(bank)[0] - 1) < 6 * math.sqrt(2.0 / n_eff)
+
+
+def _triggers_brute(z, w, thr, window):
+    D, T, n = z.shape
+    W = (n + window - 1) // window
+    snr = np.zeros((D, T, W), np.float32)
+    idx = np.full((D, T, W), -1, np.int32)
+    thr2 = np.float32(thr) * np.float32(thr)
+    for det in range(D):
+        for i in range(n):
+            best, bt = np.float32(-1), -1
+            for t in range(T):
+                re, im = np.float32(z[det, t, i].real), np.float32(z[det, t, i].imag)
+                r2 = np.float32(np.float32(np.float32(re * re) + np.float32(im * im)) * np.float32(w[t]))
+                if r2 > best:
+                    best, bt = r2, t
+            if best > thr2:
+                wd = i // window
+                cur = snr[det, bt, wd] if idx[det, bt, wd] >= 0 else np.float32(-1)
+                if best > cur:
+                    snr[det, bt, wd], idx[det, bt, wd] = best, i
+    got = idx >= 0
+    snr[got] = np.sqrt(snr[got])
+    return snr, idx
+
+
+def test_triggers_brute_force_with_ties_and_threshold():
+    rng = np.random.default_rng(44)
+    D, T, n, window = 2, 5, 300, 64
+    z = ((rng.standard_normal((D, T, n)) + 1j * rng.standard_normal((D, T, n))) * 1.6).astype(np.complex64)
+    z[0, 2, 10] = z[0, 3, 10] = 9 + 9j          # tie across templates at one sample -> lower t
+    z[1, 1, 70] = z[1, 1, 75] = 8 + 8j          # tie within a template's window -> lower sample
+    w = rng.uniform(0.5, 1.5, size=T).astype(np.float32)
+    snr, idx = oracle.triggers(z, w, 4.0, window)
+    snr_b, idx_b = _triggers_brute(z, w, 4.0, window)
+    assert np.array_equal(idx, idx_b) and np.array_equal(snr, snr_b)
+    assert idx[0, 2, 0] == 10 and idx[0, 3, 0] != 10
+    assert idx[1, 1, 1] == 70
+    # every trigger is above threshold and at most one per (template, window)
+    assert np.all(snr[idx >= 0] > 4.0) and np.all(snr[idx < 0] == 0)
