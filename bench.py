@@ -38,6 +38,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_src, per_launch_key):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or None when
+    the kernel source changed after the counters were taken (its SHA-256 differs)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "scan_fp32_traffic.json")
+    src = os.path.join(ROOT, "paper_2011_06787_amd", "csrc", kernel_src)
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get(per_launch_key)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -59,6 +77,8 @@ def parse():
     p.add_argument("--batching-only", action="store_true")
     p.add_argument("--batching-packets", type=int, default=240)
     p.add_argument("--no-tune", action="store_true", help="batching: skip the autotuner")
+    p.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
+    p.add_argument("--diff-only", action="store_true")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB four times "
                         "(calibrates the HBM byte counters) and exit")
@@ -213,6 +233,69 @@ def batching_run(args, dev):
     return out
 
 
+def differentiation_run(args, dev):
+    """Differentiation workload: 256 templates x 512 filters driven by an impulse of 8192
+    samples, targets = chirps; forward (with checkpoints every 2048 samples) and the
+    reverse-time adjoint, timed with events; gradient of the mean overlap loss checked
+    against the oracle's closed form on 16 seeded templates."""
+    import torch
+    import oracle
+    from paper_2011_06787_amd import spiir
+    w = synth.differentiation()
+    bank, n = w.bank, w.n_samples
+    target = synth.chirp_targets(0, bank.n_templates, n)
+    x = torch.from_numpy(w.input()).to(dev)
+    g = torch.from_numpy(target).to(dev)
+    sb = spiir.SpiirBank.from_bank(bank, max_chunk=n, ckpt_stride=2048)
+    a = torch.from_numpy(bank.a).to(dev)
+    b = torch.from_numpy(bank.b).to(dev)
+    sb.set_coeffs(a, b)
+
+    def loss_grad(z):
+        zz = z[0].detach().requires_grad_(True)
+        c = torch.sum(torch.conj(g) * zz, dim=-1)
+        ov = c.abs() / (torch.linalg.vector_norm(zz, dim=-1) * torch.linalg.vector_norm(g, dim=-1))
+        torch.mean(1 - ov).backward()
+        return zz.grad.unsqueeze(0).contiguous()
+
+    z, ckpt = sb.forward(x)
+    gz = loss_grad(z)
+    ga, gb = sb.backward(x, gz, ckpt)          # warm-up
+    torch.cuda.synchronize()
+    reps = 5
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        z, ckpt = sb.forward(x, z, ckpt)
+    e[1].record()
+    for _ in range(reps):
+        ga, gb = sb.backward(x, gz, ckpt, ga, gb)
+    e[2].record()
+    torch.cuda.synchronize()
+    fwd_ms, bwd_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+    upd = bank.n_filters * n
+    pick = sorted(np.random.default_rng(7).choice(bank.n_templates, 16, replace=False).tolist())
+    sub = bank.subset(pick)
+    _, ga_ref, gb_ref = oracle.overlap_grad(sub, target[pick], mode=0, scale=1.0 / bank.n_templates)
+    idx = np.concatenate([np.arange(bank.offsets[t], bank.offsets[t + 1]) for t in pick])
+    ga_h, gb_h = ga.cpu().numpy()[idx], gb.cpu().numpy()[idx]
+    rel = lambda u, v: float(np.linalg.norm(u - v) / np.linalg.norm(v))
+    out = {"workload": "differentiation: 256 templates x 512 filters, impulse input of 8192 samples, "
+                       "chirp targets, checkpoints every 2048 samples",
+           "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+           "forward_updates_per_s": upd / (fwd_ms * 1e-3),
+           "backward_updates_per_s": upd / (bwd_ms * 1e-3),
+           "backward_over_forward": bwd_ms / fwd_ms,
+           "grad_a_rel_err": rel(ga_h, ga_ref), "grad_b_rel_err": rel(gb_h, gb_ref),
+           "templates_checked": len(pick), "checkpoint_bytes": int(ckpt.numel() * 8)}
+    log(f"differentiation: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms, "
+        f"grad rel err a {out['grad_a_rel_err']:.2e} b {out['grad_b_rel_err']:.2e}")
+    sb.close()
+    del sb
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -232,6 +315,9 @@ def main():
         return
     if args.batching_only:
         print(json.dumps({"batching": batching_run(args, dev)}), flush=True)
+        return
+    if args.diff_only:
+        print(json.dumps({"differentiation": differentiation_run(args, dev)}), flush=True)
         return
     w = synth.realistic()
     bank = w.bank
@@ -313,7 +399,7 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "alg_hbm_GBps": alg_bytes / kern_avg_s / 1e9,
             "hbm_frac": alg_bytes / kern_avg_s / 1e9 / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": measured_traffic("scan_fp32.hip", "hbm_bytes_per_launch"),
         },
     }
 
@@ -355,6 +441,8 @@ def main():
         result["precision"] = precision_comparison(args, dev)
     if not args.no_batching:
         result["batching"] = batching_run(args, dev)
+    if not args.no_diff:
+        result["differentiation"] = differentiation_run(args, dev)
     print(json.dumps(result), flush=True)
 
 

@@ -173,6 +173,13 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
         return slices[p % bk.n_slices].n_slots > slices[q % bk.n_slices].n_slots;
     });
     SPIIR_TRY(upload(bk.d_order, order, s));
+    std::vector<int32_t> sorder(bk.n_slices);
+    std::iota(sorder.begin(), sorder.end(), 0);
+    std::stable_sort(sorder.begin(), sorder.end(), [&](int32_t p, int32_t q) {
+        return slices[p].n_slots > slices[q].n_slots;
+    });
+    SPIIR_TRY(dev_alloc(bk, &bk.d_slice_order, std::max<int64_t>(bk.n_slices, 1)));
+    SPIIR_TRY(upload(bk.d_slice_order, sorder, s));
     SPIIR_TRY(upload(bk.d_a, ha, s));
     SPIIR_TRY(upload(bk.d_b, hb, s));
     SPIIR_TRY(upload(bk.d_delay, hd, s));

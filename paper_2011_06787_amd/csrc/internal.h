@@ -88,6 +88,7 @@ struct Bank {
     ScanQueue *d_queue = nullptr;
     uint32_t *d_flags = nullptr; // [D][n_slices]: tiles completed (epoch-relative)
     int32_t *d_order = nullptr;  // [D*n_slices]: det*n_slices + slice, largest slices first
+    int32_t *d_slice_order = nullptr;  // [n_slices]: slices, largest first
 
     // block form (split-bf16 matrix-core products)
     int32_t hist_pad = 0;        // history samples kept in the split input, multiple of 16

@@ -113,7 +113,8 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, float2 *
 template <int MAXM>
 __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
-    float2 *__restrict__ state, const Slice *__restrict__ slices, int32_t n_slices,
+    float2 *__restrict__ state, const Slice *__restrict__ slices,
+    const int32_t *__restrict__ slice_order, int32_t n_slices,
     int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
     int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, int32_t tile_len,
     int32_t win_floats, float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg) {
@@ -125,8 +126,10 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     const int lane = threadIdx.x % kWave;
     float2 *red = reinterpret_cast<float2 *>(smem + win_floats) + wave * kWave * kRedStride;
     const int det = blockIdx.y;
-    const int sidx = blockIdx.x * kScanWaves + wave;
-    const bool active = sidx < n_slices;
+    // slices go out largest first, so the waves of a workgroup carry equal work
+    const int rank = blockIdx.x * kScanWaves + wave;
+    const bool active = rank < n_slices;
+    const int sidx = active ? __builtin_amdgcn_readfirstlane(slice_order[rank]) : 0;
     Slice sl = active ? slices[sidx] : Slice{0, 0, 0, 0};
     sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
     sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
@@ -396,7 +399,7 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
         const dim3 grid((bk.n_slices + kScanWaves - 1) / kScanWaves, bk.n_det);
         hipLaunchKernelGGL(scan_fp32_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
                            scan_fp32_lds_bytes(tile, bk.hist_len), s, bk.d_a, bk.d_b, bk.d_delay,
-                           bk.d_state, bk.d_slices, bk.n_slices, lanes, x, n, bk.d_hist,
+                           bk.d_state, bk.d_slices, bk.d_slice_order, bk.n_slices, lanes, x, n, bk.d_hist,
                            bk.hist_len, bk.d_partial, bk.max_chunk, tile, win_floats, ckpt,
                            bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride);
     }

@@ -101,3 +101,19 @@ def test_differentiation_rejected_in_block_mode(gpu):
     with gpu.SpiirBank.from_bank(bank, max_chunk=256, mode=gpu.MODE_BF16_BLOCK) as sb:
         with pytest.raises(gpu.SpiirError):
             sb.forward(torch.zeros((1, 256), device="cuda"))
+
+
+def test_fitting_raises_the_overlap(gpu):
+    """Coefficient fitting with the adjoint (Adam on a, b): the mean overlap with the
+    chirp targets increases."""
+    import torch
+    from paper_2011_06787_amd import fit
+    w = synth.differentiation(n_templates=8, per_template=64, n_samples=2048)
+    target = torch.from_numpy(synth.chirp_targets(0, 8, 2048)).cuda()
+    with gpu.SpiirBank.from_bank(w.bank, max_chunk=2048, ckpt_stride=512) as sb:
+        res = fit.fit(sb, torch.from_numpy(w.bank.a).cuda(), torch.from_numpy(w.bank.b).cuda(),
+                      target, steps=30, lr=3e-3)
+    h = res["overlap_history"]
+    print(f"overlap {h[0]:.4f} -> {h[-1]:.4f}")
+    assert h[-1] > h[0]
+    assert float(res["a"].abs().max()) < 1.0

@@ -54,6 +54,7 @@ def test_triggers_end_to_end_on_noise(gpu):
     snr, idx = snr.cpu().numpy(), idx.cpu().numpy()
     d, t, k = np.nonzero(idx >= 0)
     assert len(d) > 0
-    vals = np.abs(zc[d, t, k * 2048 + idx[d, t, k]]) * np.sqrt(2.0 / power[t])
+    vals = np.abs(zc[d, t, idx[d, t, k]]) * np.sqrt(2.0 / power[t])   # index is in [0, n)
+    assert np.all(idx[d, t, k] // 2048 == k)
     assert np.allclose(snr[d, t, k], vals, rtol=1e-5)
     assert np.all(snr[d, t, k] > 4.0)
