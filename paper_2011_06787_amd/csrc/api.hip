@@ -164,6 +164,7 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
                         std::max<int64_t>((int64_t)bk.n_det * bk.n_slices * bk.max_chunk, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_queue, 1));
     SPIIR_TRY(dev_alloc(bk, &bk.d_flags, std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 4)));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_slice_head, std::max<int64_t>(2 * (int64_t)bk.n_det, 4)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_order, std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 1)));
     // persistent-scan hand-out order inside a time tile: largest slices first
     std::vector<int32_t> order((size_t)bk.n_det * bk.n_slices);
@@ -211,6 +212,9 @@ spiir_status zero_queue(spiir::Bank &bk, hipStream_t s) {
     SPIIR_HIP(spiir::launch_zero(bk.d_flags,
                                  round16(std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 4) *
                                          (int64_t)sizeof(uint32_t)), s));
+    SPIIR_HIP(spiir::launch_zero(bk.d_slice_head,
+                                 round16(std::max<int64_t>(2 * (int64_t)bk.n_det, 4) *
+                                         (int64_t)sizeof(uint32_t)), s));
     return SPIIR_OK;
 }
 
@@ -231,6 +235,7 @@ void spiir_opts_default(spiir_opts *opts) {
     opts->block_len = 128;
     opts->long_pole_abs_a = 0.999;
     opts->ckpt_stride = 2048;
+    opts->queue_wgs = 2;
 }
 
 const char *spiir_last_error(void) { return g_error.c_str(); }
@@ -281,6 +286,8 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         if (time_tile != -1 && time_tile != 0 &&
             (time_tile < spiir::kSub || time_tile > 4096 || time_tile % spiir::kSub != 0))
             return fail(SPIIR_E_INVAL, "time_tile must be -1, 0 or a multiple of 16 in [16, 4096]");
+        if (opts.queue_wgs < 0 || opts.queue_wgs > 8)
+            return fail(SPIIR_E_INVAL, "queue_wgs must be in [0, 8]");
         int32_t dmax = 0;
         for (int64_t k = 0; k < F; ++k) {
             const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
@@ -313,6 +320,9 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         bk.mode = opts.mode;
         bk.fpl = fpl;
         bk.time_tile = time_tile > 0 ? time_tile : 0;
+        bk.queue_per_cu = opts.queue_wgs > 0 ? opts.queue_wgs : 2;
+        bk.slice_queue = time_tile == 0 &&
+                         (int64_t)bk.max_chunk + hist_len + spiir::kSub <= spiir::kWindowFloats;
         bk.block_len = block_len;
         bk.ckpt_stride = ckpt_stride;
         bk.h_offsets.assign(offsets, offsets + n_templates + 1);
@@ -332,6 +342,15 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
             std::string err;
             st = spiir::plan_block(bk, offsets, a, b, delay, s, err);
             if (st != SPIIR_OK) fail(st, err);
+            if (st == SPIIR_OK) {
+                if (spiir::block_state_lds_bytes(bk) > 150 * 1024) {
+                    st = fail(SPIIR_E_UNSUPPORTED, "block form: input band too wide for LDS");
+                } else {
+                    const hipError_t e = spiir::prepare_block_bf16(bk);
+                    if (e != hipSuccess)
+                        st = fail(SPIIR_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+                }
+            }
         } else if (st == SPIIR_OK) {
             st = plan_scan(bk, offsets, a, b, delay, s);
             if (st == SPIIR_OK) {
@@ -442,6 +461,7 @@ spiir_status spiir_bank_get_info(const spiir_bank *h, spiir_bank_info *info) {
     info->filters_per_lane = bk.fpl;
     info->time_tile = bk.time_tile;
     info->scan_waves = bk.scan_waves;
+    info->queue_wgs = bk.slice_queue ? bk.queue_wgs : 0;
     info->block_len = bk.block_len;
     info->n_long_pole = bk.n_long_pole;
     if (bk.d_queue != nullptr) {

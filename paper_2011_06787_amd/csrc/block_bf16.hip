@@ -121,8 +121,8 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
         }
     }
     tot[q][f] = y;
-    // one wave per workgroup and the four lanes of a filter take the same branch, so
-    // a wave-level LDS ordering fence (no barrier) is enough here
+    // sl and tot belong to this wave alone and the four lanes of a filter take the same
+    // branch, so a wave-level LDS ordering fence (no barrier) is enough here
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     // combine the group totals: state entering each group, and the chunk's exit state
     C2<R> ystart = y_prev, ynext = y_prev;
@@ -149,83 +149,124 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
     }
 }
 
-// One wave per (tile of 16 filters, detector): S for all blocks, kChunk blocks (two
-// 32-column MFMA tiles sharing each A fragment) per pass, then the carry.
-__global__ __launch_bounds__(kWave) void block_state_kernel(
-    const WTile *__restrict__ tiles, const BTemplate *__restrict__ tmpls,
+// One workgroup of kStateWaves waves per (kStateWaves consecutive tiles, detector);
+// wave w owns tile blockIdx.x*kStateWaves + w (16 filters).  For every chunk of kChunk
+// blocks the workgroup stages the input range all its tiles read,
+//     x[c0 L + P_lo, (c0 + kChunk - 1) L + P_hi)     (P_lo, P_hi: union band of the tiles)
+// once into LDS (hi and lo planes), skewed by 8 elements per row of L so that the
+// 16-byte fragments of consecutive blocks (columns) start 4 banks apart; the MFMA B
+// fragments are then LDS reads instead of strided global reads.  Each wave computes S
+// for its tile (two 32-column MFMA tiles sharing each A fragment).  After a barrier the
+// same LDS holds the waves' S rows for the carry, so the footprint is the larger of the
+// two uses and several workgroups share a CU.
+constexpr int kStateWaves = 4;
+constexpr int kSlFloats = 32 * (kChunk + 1);   // one wave's S rows
+
+__device__ __forceinline__ int skew(int p, int L) { return p + 8 * (p / L); }
+
+__global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
+    const WTile *__restrict__ tiles, int32_t n_tiles, const BTemplate *__restrict__ tmpls,
     const uint16_t *__restrict__ wa, const uint16_t *__restrict__ xs, int64_t xs_stride,
-    int32_t hist_pad, int32_t n_det, int32_t L, int32_t nb, int32_t nb_max,
-    const double2 *__restrict__ aL, const int32_t *__restrict__ lp, double2 *__restrict__ state,
-    int64_t n_fpad, uint16_t *__restrict__ yt, int64_t y_per_det) {
-    __shared__ float sl[32][kChunk + 1];
-    __shared__ C2<double> tot64[4][16];
-    __shared__ C2<float> tot32[4][16];
-    const int lane = threadIdx.x;
-    const WTile tl = tiles[blockIdx.x];
+    int32_t hist_pad, int32_t n_det, int32_t L, int32_t nb, const double2 *__restrict__ aL,
+    const int32_t *__restrict__ lp, double2 *__restrict__ state, int64_t n_fpad,
+    uint16_t *__restrict__ yt, int64_t y_per_det, int32_t xwin) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t lds[];   // staged input / S rows
+    __shared__ C2<double> tot64[kStateWaves][4][16];
+    __shared__ C2<float> tot32[kStateWaves][4][16];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
     const int det = blockIdx.y;
+    const int tile0 = blockIdx.x * kStateWaves;
+    const int tile_id = tile0 + wave;
+    const bool active = tile_id < n_tiles;
+    const WTile tl = tiles[active ? tile_id : tile0];
     const BTemplate bt = tmpls[tl.tmpl];
+    // union band of the workgroup's tiles (multiples of 16)
+    int p_lo = 1 << 30, p_hi = -(1 << 30);
+    for (int id = tile0; id < min(n_tiles, tile0 + kStateWaves); ++id) {
+        const WTile tw = tiles[id];
+        p_lo = min(p_lo, tw.sigma_lo);
+        p_hi = max(p_hi, tw.sigma_lo + 16 * tw.nks);
+    }
     const uint16_t *xh = xs + (int64_t)det * xs_stride + hist_pad;
     const uint16_t *xl = xh + (int64_t)n_det * xs_stride;
+    uint16_t *sh = lds;
+    uint16_t *slo = lds + xwin;
+    float(*sl)[kChunk + 1] =
+        reinterpret_cast<float(*)[kChunk + 1]>(reinterpret_cast<float *>(lds) + wave * kSlFloats);
     const int col = lane % 32;
     const int kg = (lane / 32) * 8;
     const uint16_t *ap = wa + tl.a_off + (lane % 32) * 16 + kg;
 
-    // carry lanes: filter f of the tile, group q of the chunk's blocks
     const int f = lane & 15;
     const int q = lane >> 4;
     const int64_t gf = tl.g0 + f;
-    const double2 ys = state[(int64_t)det * n_fpad + gf];
-    const double2 ta = aL[gf];
-    const bool long_pole = lp[gf] != 0;
+    const double2 ys = active ? state[(int64_t)det * n_fpad + gf] : make_double2(0.0, 0.0);
+    const double2 ta = active ? aL[gf] : make_double2(0.0, 0.0);
+    const bool long_pole = active && lp[gf] != 0;
     C2<double> y64{ys.x, ys.y};
     C2<float> y32{(float)ys.x, (float)ys.y};
     const C2<double> A64{ta.x, ta.y};
     const C2<float> A32{(float)ta.x, (float)ta.y};
-    const int64_t row_len2 = bt.fpad;   // 32-bit (re, im) pairs per block row
+    const int64_t row_len2 = bt.fpad;
     uint32_t *yh = reinterpret_cast<uint32_t *>(yt + (int64_t)det * y_per_det + bt.y_off) + tl.f0 + f;
     uint32_t *yl = reinterpret_cast<uint32_t *>(yt + (int64_t)(n_det + det) * y_per_det + bt.y_off) +
                    tl.f0 + f;
 
     for (int c0 = 0; c0 < nb; c0 += kChunk) {
-        f32x16 acc[2] = {};
-        bool valid[2];
-        int64_t pbase[2];
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            const int b = c0 + ct * 32 + col;
-            valid[ct] = b < nb;
-            pbase[ct] = (int64_t)(valid[ct] ? b : 0) * L + tl.sigma_lo + kg;
+        const int cols = min(kChunk, nb - c0);
+        const int span = (cols - 1) * L + (p_hi - p_lo);   // multiple of 16
+        const int64_t g0 = (int64_t)c0 * L + p_lo;
+        __syncthreads();   // previous chunk's S rows no longer read
+        for (int e = threadIdx.x; e < span / 8 * 2; e += blockDim.x) {
+            const int plane = e & 1;
+            const int pp = (e >> 1) * 8;
+            const bf16x8 v = load8((plane ? xl : xh) + g0 + pp);
+            *reinterpret_cast<bf16x8 *>((plane ? slo : sh) + skew(pp, L)) = v;
         }
-        for (int ks = 0; ks < tl.nks; ++ks) {
-            const bf16x8 ah = load8(ap + (int64_t)ks * 1024);
-            const bf16x8 al = load8(ap + (int64_t)ks * 1024 + 512);
+        __syncthreads();
+        f32x16 acc[2] = {};
+        if (active) {
+            bool valid[2];
+            int rel[2];
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
-                bf16x8 bh = {}, bl = {};
-                if (valid[ct]) {
-                    bh = load8(xh + pbase[ct] + 16 * ks);
-                    bl = load8(xl + pbase[ct] + 16 * ks);
+                const int b = ct * 32 + col;
+                valid[ct] = b < cols;
+                rel[ct] = (valid[ct] ? b : 0) * L + tl.sigma_lo - p_lo + kg;
+            }
+            for (int ks = 0; ks < tl.nks; ++ks) {
+                const bf16x8 ah = load8(ap + (int64_t)ks * 1024);
+                const bf16x8 al = load8(ap + (int64_t)ks * 1024 + 512);
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    bf16x8 bh = {}, bl = {};
+                    if (valid[ct]) {
+                        const int o = skew(rel[ct] + 16 * ks, L);
+                        bh = *reinterpret_cast<const bf16x8 *>(sh + o);
+                        bl = *reinterpret_cast<const bf16x8 *>(slo + o);
+                    }
+                    acc[ct] = mma3(ah, al, bh, bl, acc[ct]);
                 }
-                acc[ct] = mma3(ah, al, bh, bl, acc[ct]);
             }
         }
+        __syncthreads();   // staged input no longer read: the LDS now holds S rows
+        if (active) {
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+            for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                sl[8 * (i / 4) + 4 * (lane / 32) + (i % 4)][ct * 32 + col] = acc[ct][i];
-        __syncthreads();
-        const int valid_cols = min(kChunk, nb - c0);
-        if (long_pole)
-            carry_chunk<double>(sl, tot64, f, q, valid_cols, A64, y64, yh, yl, row_len2, c0);
-        else
-            carry_chunk<float>(sl, tot32, f, q, valid_cols, A32, y32, yh, yl, row_len2, c0);
-        __syncthreads();
+                for (int i = 0; i < 16; ++i)
+                    sl[8 * (i / 4) + 4 * (lane / 32) + (i % 4)][ct * 32 + col] = acc[ct][i];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            if (long_pole)
+                carry_chunk<double>(sl, tot64[wave], f, q, cols, A64, y64, yh, yl, row_len2, c0);
+            else
+                carry_chunk<float>(sl, tot32[wave], f, q, cols, A32, y32, yh, yl, row_len2, c0);
+        }
     }
-    if (q == 0)
+    if (active && q == 0)
         state[(int64_t)det * n_fpad + gf] =
             long_pole ? make_double2(y64.r, y64.i) : make_double2((double)y32.r, (double)y32.i);
-    (void)nb_max;
 }
 
 // Output product, one workgroup of (2L/64) waves per (template, 128 columns); a
@@ -356,6 +397,26 @@ __global__ __launch_bounds__(512) void block_output_kernel(
 
 }  // namespace
 
+// LDS elements per plane of the staged input of block_state_kernel: the widest union
+// band of a workgroup's tiles plus kChunk-1 blocks, skewed (8 per L elements).
+int32_t block_state_xwin(const Bank &bk) {
+    const int L = bk.block_len;
+    const int span = (kChunk - 1) * L + bk.max_wg_band;
+    return (int32_t)((span + 8 * (span / L + 1) + 15) / 16 * 16);
+}
+
+// dynamic LDS of block_state_kernel: the staged input and, reusing it, the S rows
+size_t block_state_lds_bytes(const Bank &bk) {
+    return std::max<size_t>((size_t)2 * block_state_xwin(bk) * sizeof(uint16_t),
+                            (size_t)kStateWaves * kSlFloats * sizeof(float));
+}
+
+hipError_t prepare_block_bf16(const Bank &bk) {
+    return hipFuncSetAttribute((const void *)block_state_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)block_state_lds_bytes(bk));
+}
+
 hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *z, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int L = bk.block_len;
@@ -366,11 +427,15 @@ hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *
                            dim3(256), 0, s, x, n, bk.d_hist, bk.hist_len, bk.hist_pad, bk.d_xs,
                            bk.xs_stride, bk.n_det);
     }
-    if (bk.n_wtiles > 0)
-        hipLaunchKernelGGL(block_state_kernel, dim3(bk.n_wtiles, bk.n_det), dim3(kWave), 0, s,
-                           bk.d_wtiles, bk.d_btmpl, bk.d_wa, bk.d_xs, bk.xs_stride, bk.hist_pad,
-                           bk.n_det, L, nb, bk.max_chunk / L, bk.d_aL, bk.d_lp, bk.d_state64,
-                           bk.n_fpad, bk.d_yt, bk.y_per_det);
+    if (bk.n_wtiles > 0) {
+        const int32_t xwin = block_state_xwin(bk);
+        hipLaunchKernelGGL(block_state_kernel,
+                           dim3((bk.n_wtiles + kStateWaves - 1) / kStateWaves, bk.n_det),
+                           dim3(kWave * kStateWaves), block_state_lds_bytes(bk), s,
+                           bk.d_wtiles, bk.n_wtiles, bk.d_btmpl, bk.d_wa, bk.d_xs, bk.xs_stride,
+                           bk.hist_pad, bk.n_det, L, nb, bk.d_aL, bk.d_lp, bk.d_state64, bk.n_fpad,
+                           bk.d_yt, bk.y_per_det, xwin);
+    }
     const int ncols = bk.n_det * nb;
     const int col_tiles = (ncols + kOutCols - 1) / kOutCols;
     const int64_t groups = (bk.n_templates + kXcds - 1) / kXcds;

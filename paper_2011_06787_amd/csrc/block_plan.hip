@@ -110,6 +110,17 @@ spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const 
         }
     }
     tile_base[T] = (int64_t)tiles.size();
+    // widest input band of a group of 4 consecutive tiles (one block_state workgroup)
+    int32_t band = 0;
+    for (size_t i = 0; i < tiles.size(); i += 4) {
+        int32_t lo = 1 << 30, hi = -(1 << 30);
+        for (size_t j = i; j < std::min(tiles.size(), i + 4); ++j) {
+            lo = std::min(lo, tiles[j].sigma_lo);
+            hi = std::max(hi, tiles[j].sigma_lo + 16 * tiles[j].nks);
+        }
+        band = std::max(band, hi - lo);
+    }
+    bk.max_wg_band = band;
     bk.n_fpad = g;
     bk.y_per_det = std::max<int64_t>(yoff, 32);
     bk.n_wtiles = (int32_t)tiles.size();

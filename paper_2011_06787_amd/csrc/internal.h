@@ -71,6 +71,9 @@ struct Bank {
     int32_t scan_tile = 2048;  // samples per LDS input window of the one-shot FP32 scan
     int32_t time_tile = 256;   // samples per work item of the persistent scan; 0 = one-shot
     int32_t scan_waves = 0;    // resident waves of the persistent scan (grid size)
+    bool slice_queue = false;  // one-shot scan hands slices out through a work queue
+    int32_t queue_per_cu = 2;  // requested resident workgroups per compute unit (slice queue)
+    int32_t queue_wgs = 0;     // workgroups per detector of the slice-queue scan
     int32_t ckpt_stride = 2048;  // differentiation: samples per checkpoint segment
 
     // FP32 scan layout
@@ -87,12 +90,14 @@ struct Bank {
     float2 *d_partial = nullptr; // [D][n_slices][max_chunk]
     ScanQueue *d_queue = nullptr;
     uint32_t *d_flags = nullptr; // [D][n_slices]: tiles completed (epoch-relative)
+    uint32_t *d_slice_head = nullptr;  // [2][D]: slice-queue head and finished waves per detector
     int32_t *d_order = nullptr;  // [D*n_slices]: det*n_slices + slice, largest slices first
     int32_t *d_slice_order = nullptr;  // [n_slices]: slices, largest first
 
     // block form (split-bf16 matrix-core products)
     int32_t hist_pad = 0;        // history samples kept in the split input, multiple of 16
     int32_t n_wtiles = 0;
+    int32_t max_wg_band = 0;     // widest input band over groups of 4 consecutive tiles
     int64_t n_fpad = 0;          // filters in sorted-padded order
     int64_t y_per_det = 0;       // state-row elements per detector (NBmax * sum 2*fpad)
     int32_t n_long_pole = 0;
@@ -142,6 +147,9 @@ hipError_t launch_triggers(const float2 *z, int32_t n_det, int32_t n_templates, 
                            const float *weight, float threshold, int32_t window,
                            unsigned long long *work, float *snr, int32_t *index, hipStream_t s);
 hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *z, hipStream_t s);
+int32_t block_state_xwin(const Bank &bk);
+size_t block_state_lds_bytes(const Bank &bk);
+hipError_t prepare_block_bf16(const Bank &bk);
 spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const float *b,
                         const int32_t *delay, hipStream_t s, std::string &err);
 

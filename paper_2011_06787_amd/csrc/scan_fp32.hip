@@ -15,7 +15,14 @@
 // template sum for the sub-tile.  A second kernel adds the slices of each template.
 //
 // Arithmetic per filter-sample: 2 mul + 4 fma (complex a*y + b*x with real x)
-// and 2 adds into the lane sum: 8 VALU lane-operations for the paper's 12 flops.
+// and 2 adds into the lane sum (none for a lane's first filter): at most 8 VALU
+// lane-operations for the paper's 12 flops.
+//
+// Schedules.  The static kernel gives one slice to each wave.  When the packet and
+// its history fit one LDS window, the slice-queue kernel instead keeps a fixed
+// number of workgroups resident and lets every wave take the next slice (largest
+// first) from a per-detector counter until none is left, so the compute units
+// finish together however the slice count divides over them.
 #include <algorithm>
 
 #include "internal.h"
@@ -65,12 +72,16 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, float2 *
                                          const float (&br)[MAXM], const float (&bi)[MAXM],
                                          const int (&base)[MAXM], float (&yr)[MAXM],
                                          float (&yi)[MAXM], float2 *__restrict__ out) {
+    // every caller has m >= 1: in a full sub-tile the lane sums start from the first
+    // filter's outputs (no zero fill, no first add)
     float2 acc[kSub];
+    if (TAIL) {
 #pragma unroll
-    for (int s = 0; s < kSub; ++s) acc[s] = make_float2(0.0f, 0.0f);
+        for (int s = 0; s < kSub; ++s) acc[s] = make_float2(0.0f, 0.0f);
+    }
 #pragma unroll
     for (int j = 0; j < MAXM; ++j) {
-        if (j < m) {  // wave-uniform
+        if (j == 0 || j < m) {  // wave-uniform
             const float *xp = win + base[j] + s0;
             float r = yr[j], im = yi[j];
 #pragma unroll
@@ -81,8 +92,12 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, float2 *
                     const float ni = fmaf(ar[j], im, fmaf(ai[j], r, bi[j] * xv));
                     r = nr;
                     im = ni;
-                    acc[s].x += r;
-                    acc[s].y += im;
+                    if (!TAIL && j == 0) {
+                        acc[s] = make_float2(r, im);
+                    } else {
+                        acc[s].x += r;
+                        acc[s].y += im;
+                    }
                 }
             }
             yr[j] = r;
@@ -188,6 +203,92 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
 #pragma unroll
         for (int j = 0; j < MAXM; ++j)
             if (j < m) st[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+    }
+}
+
+// Slice-queue variant of the one-shot scan: the window x[-hist_len, n) of the
+// workgroup's detector is loaded once, then every wave repeatedly takes the next
+// slice from head[det] (slices largest first) and walks the whole packet for it.
+// done[det] counts the waves that found the queue empty; the last of them rewinds
+// both counters for the next launch (kernel boundaries order that with it).
+template <int MAXM>
+__global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_queue_kernel(
+    const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
+    float2 *__restrict__ state, const Slice *__restrict__ slices,
+    const int32_t *__restrict__ slice_order, int32_t n_slices, int32_t n_det,
+    int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
+    int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, int32_t win_floats,
+    float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg, uint32_t *__restrict__ head) {
+    extern __shared__ float smem[];
+    float *win = smem;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    float2 *red = reinterpret_cast<float2 *>(smem + win_floats) + wave * kWave * kRedStride;
+    const int det = blockIdx.y;
+    const float *xd = x + (int64_t)det * n;
+    const float *hd = hist + (int64_t)det * hist_len;
+    load_window(win, xd, hd, hist_len, 0, n, threadIdx.x, blockDim.x);
+    __syncthreads();
+    float2 *st = state + (int64_t)det * lanes_total;
+    float2 *ck = ckpt != nullptr ? ckpt + (int64_t)det * n_seg * lanes_total : nullptr;
+    for (;;) {
+        uint32_t r = 0;
+        if (lane == 0)
+            r = __hip_atomic_fetch_add(head + det, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        r = __builtin_amdgcn_readfirstlane(r);
+        if (r >= (uint32_t)n_slices) break;
+        const int sidx = __builtin_amdgcn_readfirstlane(slice_order[r]);
+        Slice sl = slices[sidx];
+        sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
+        sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
+        const int m = sl.n_slots;
+        float ar[MAXM], ai[MAXM], br[MAXM], bi[MAXM], yr[MAXM], yi[MAXM];
+        int base[MAXM];
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+            if (j < m) {
+                const int64_t g = (int64_t)(sl.slot_base + j) * kWave + lane;
+                const float2 a = ca[g], b = cb[g], y = st[g];
+                ar[j] = a.x; ai[j] = a.y; br[j] = b.x; bi[j] = b.y; yr[j] = y.x; yi[j] = y.y;
+                base[j] = hist_len - cd[g];
+            } else {
+                ar[j] = ai[j] = br[j] = bi[j] = yr[j] = yi[j] = 0.0f;
+                base[j] = 0;
+            }
+        }
+        if (ck != nullptr) {
+#pragma unroll
+            for (int j = 0; j < MAXM; ++j)
+                if (j < m) ck[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+        }
+        float2 *pout = partial + ((int64_t)det * n_slices + sidx) * part_stride;
+        int s0 = 0;
+        for (; s0 + kSub <= n; s0 += kSub) {
+            sub_tile<MAXM, false>(win, red, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
+                                  pout + s0);
+            const int e = s0 + kSub;
+            if (ck != nullptr && e % ckpt_stride == 0 && e < n) {
+                float2 *cs = ck + (int64_t)(e / ckpt_stride) * lanes_total;
+#pragma unroll
+                for (int j = 0; j < MAXM; ++j)
+                    if (j < m) cs[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+            }
+        }
+        if (s0 < n)
+            sub_tile<MAXM, true>(win, red, lane, m, s0, n - s0, ar, ai, br, bi, base, yr, yi,
+                                 pout + s0);
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j)
+            if (j < m) st[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+    }
+    if (lane == 0) {
+        uint32_t *done = head + n_det;
+        const uint32_t old =
+            __hip_atomic_fetch_add(done + det, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gridDim.x * kScanWaves - 1) {
+            __hip_atomic_store(head + det, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(done + det, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -358,23 +459,45 @@ size_t scan_persistent_lds_bytes(int32_t tile, int32_t hist_len) {
 
 namespace {
 
+hipError_t device_cus(int &cus) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    return hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+}
+
 template <int MAXM>
 hipError_t prepare_fpl(Bank &bk) {
     hipError_t e = hipFuncSetAttribute((const void *)scan_fp32_kernel<MAXM>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)scan_fp32_lds_bytes(bk.scan_tile, bk.hist_len));
-    if (e != hipSuccess || bk.time_tile <= 0) return e;
+    if (e != hipSuccess) return e;
+    if (bk.slice_queue) {
+        // resident workgroups: queue_wgs per compute unit (at most what fits), shared
+        // out over the detectors
+        const int lds = (int)scan_fp32_lds_bytes(bk.max_chunk, bk.hist_len);
+        e = hipFuncSetAttribute((const void *)scan_fp32_queue_kernel<MAXM>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        int per_cu = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, (const void *)scan_fp32_queue_kernel<MAXM>, kWave * kScanWaves, lds);
+        if (e != hipSuccess) return e;
+        e = device_cus(cus);
+        if (e != hipSuccess) return e;
+        const int64_t want = (int64_t)std::max(1, std::min(bk.queue_per_cu, per_cu)) * std::max(1, cus);
+        bk.queue_wgs = (int32_t)std::max<int64_t>(1, (want + bk.n_det - 1) / bk.n_det);
+    }
+    if (bk.time_tile <= 0) return hipSuccess;
     const int lds = (int)scan_persistent_lds_bytes(bk.time_tile, bk.hist_len);
     e = hipFuncSetAttribute((const void *)scan_fp32_persistent_kernel<MAXM>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    int per_cu = 0, dev = 0, cus = 0;
+    int per_cu = 0, cus = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, (const void *)scan_fp32_persistent_kernel<MAXM>, kWave, lds);
     if (e != hipSuccess) return e;
-    e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    e = device_cus(cus);
     if (e != hipSuccess) return e;
     bk.scan_waves = std::max(1, per_cu) * std::max(1, cus);
     return hipSuccess;
@@ -393,6 +516,16 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            bk.d_delay, bk.d_state, bk.d_slices, bk.d_order, bk.n_slices, bk.n_det,
                            lanes, x, n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk,
                            bk.time_tile, win_floats, bk.d_queue, bk.d_flags);
+    } else if (bk.slice_queue) {
+        const int32_t win_floats = ((n + bk.hist_len + kSub) + 3) & ~3;
+        const int64_t need = (bk.n_slices + kScanWaves - 1) / kScanWaves;
+        const dim3 grid((unsigned)std::min<int64_t>(bk.queue_wgs, need), bk.n_det);
+        hipLaunchKernelGGL(scan_fp32_queue_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
+                           scan_fp32_lds_bytes(n, bk.hist_len), s, bk.d_a, bk.d_b, bk.d_delay,
+                           bk.d_state, bk.d_slices, bk.d_slice_order, bk.n_slices, bk.n_det, lanes,
+                           x, n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk, win_floats,
+                           ckpt, bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride,
+                           bk.d_slice_head);
     } else {
         const int32_t tile = bk.scan_tile;
         const int32_t win_floats = ((tile + bk.hist_len + kSub) + 3) & ~3;

@@ -16,13 +16,15 @@ TOL_FP32 = 1e-4
 
 
 def run_stream(gpu, bank, x, chunk, *, peak_window=0, filters_per_lane=0, max_delay=0,
-               want_z=True, time_tile=0):
+               want_z=True, time_tile=0, queue_wgs=0):
     import torch
     D, N = x.shape
     zs, pk, am = [], [], []
     with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=chunk, peak_window=peak_window,
                                  filters_per_lane=filters_per_lane, max_delay=max_delay,
-                                 time_tile=time_tile) as sb:
+                                 time_tile=time_tile, queue_wgs=queue_wgs) as sb:
+        fits = chunk + sb.info.max_delay + 16 <= 12288
+        assert (sb.info.queue_wgs > 0) == (time_tile == 0 and fits)
         xd = torch.from_numpy(x).cuda()
         for lo in range(0, N, chunk):
             xc = xd[:, lo:lo + chunk].contiguous()
@@ -50,7 +52,7 @@ def test_tiny_workload_whole_and_chunked(gpu):
             check_peaks(pk[c], am[c], z[..., lo:lo + chunk], z_ref[..., lo:lo + chunk], chunk)
 
 
-@pytest.mark.parametrize("time_tile", [0, 256, 16])
+@pytest.mark.parametrize("time_tile", [0, -1, 256, 16])
 @pytest.mark.parametrize("chunk", [1, 7, 100, 512, 1000])
 def test_chunk_sizes_agree_with_oracle(gpu, chunk, time_tile):
     rng = np.random.default_rng(100 + chunk)
@@ -62,18 +64,20 @@ def test_chunk_sizes_agree_with_oracle(gpu, chunk, time_tile):
     assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
 
 
-@pytest.mark.parametrize("time_tile", [16, 256, 4096, -1])
-def test_time_tiles_on_a_larger_bank(gpu, time_tile):
-    # many slices and tiles: exercises the persistent queue's dependency chains
+@pytest.mark.parametrize("time_tile, queue_wgs", [(16, 0), (256, 0), (4096, 0), (-1, 0),
+                                                  (0, 1), (0, 2), (0, 8)])
+def test_schedules_on_a_larger_bank(gpu, time_tile, queue_wgs):
+    # many slices and tiles: the persistent queue's dependency chains, and the slice
+    # queue with few and with many resident workgroups per compute unit
     rng = np.random.default_rng(150)
     bank = synth.draw_filters(rng, rng.integers(50, 900, size=96))
     x = rng.standard_normal((3, 6144)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
-    z, pk, am = run_stream(gpu, bank, x, 2048, time_tile=time_tile)
+    z, pk, am = run_stream(gpu, bank, x, 2048, time_tile=time_tile, queue_wgs=queue_wgs)
     assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
 
 
-@pytest.mark.parametrize("time_tile", [0, 256])
+@pytest.mark.parametrize("time_tile", [0, -1, 256])
 @pytest.mark.parametrize("fpl", [2, 4, 8])
 def test_filters_per_lane_and_slice_boundaries(gpu, fpl, time_tile):
     # template sizes around the slot/slice boundaries: 64*fpl filters per slice
@@ -99,7 +103,8 @@ def test_delay_extremes_and_history(gpu):
     bank.d[5:10] = 2047
     x = rng.standard_normal((1, 6000)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
-    for chunk, md, tt in ((512, 0, 0), (300, 4000, 256), (6000, 0, 0), (6000, 0, 512), (300, 8191, 64)):
+    for chunk, md, tt in ((512, 0, 0), (300, 4000, 256), (6000, 0, 0), (6000, 0, 512), (300, 8191, 64),
+                          (300, 8191, 0), (4000, 8191, 0)):
         z, _, _ = run_stream(gpu, bank, x, chunk, max_delay=md, time_tile=tt)
         assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
 
