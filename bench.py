@@ -63,8 +63,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=4)
     p.add_argument("--filters-per-lane", type=int, default=0)
     p.add_argument("--time-tile", type=int, default=0)
-    p.add_argument("--queue-wgs", type=int, default=0,
-                   help="slice-queue scan: resident workgroups per compute unit (0 = library default)")
+    p.add_argument("--balance-wgs", type=int, default=0,
+                   help="balanced schedule: resident workgroups per compute unit (0 = off)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-check", action="store_true")
     p.add_argument("--cpu-templates", type=int, default=1024,
@@ -333,7 +333,7 @@ def main():
     chunks = [x[:, i * chunk:(i + 1) * chunk].contiguous() for i in range(n_chunks)]
     sb = spiir.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=chunk,
                                    filters_per_lane=args.filters_per_lane,
-                                   time_tile=args.time_tile, queue_wgs=args.queue_wgs)
+                                   time_tile=args.time_tile, balance_wgs=args.balance_wgs)
     z = torch.empty((D, T, chunk), dtype=torch.complex64, device=dev)
     peak = torch.empty((D, T, 1), dtype=torch.float32, device=dev)
     amax = torch.empty((D, T, 1), dtype=torch.int32, device=dev)
@@ -387,7 +387,7 @@ def main():
             "templates": T, "filters": F, "detectors": D, "packet_samples": chunk,
             "stream_samples": int(x_host.shape[1]), "filters_per_lane": info.filters_per_lane,
             "slices": info.n_slices, "time_tile": info.time_tile, "scan_waves": info.scan_waves,
-            "queue_wgs": info.queue_wgs,
+            "balance_waves": info.balance_waves,
         },
         "roofline": {
             "kernel": "scan_fp32_kernel",

@@ -65,26 +65,27 @@ typedef struct {
                                  0 = one window per packet */
     int32_t mode;             /* spiir_mode */
     int32_t filters_per_lane; /* FP32 scan: filters held per GPU lane, 2, 4 or 8; 0 = 4 */
-    int32_t time_tile;        /* FP32 scan schedule.  0: one wave per filter group walks
-                                 the whole packet; when a packet of max_chunk samples and
-                                 its history fit one LDS window, the groups are handed out
-                                 to a fixed set of resident waves through a work queue.
-                                 -1: the same without the queue (one wave per group).
-                                 16..4096 (multiple of 16): the persistent work-queue scan
-                                 with packets cut into time tiles of this many samples */
+    int32_t time_tile;        /* FP32 scan schedule.  -1 or 0: one wave per filter group
+                                 walks the whole packet (see queue_wgs).  16..4096
+                                 (multiple of 16): the persistent work-queue scan with
+                                 packets cut into time tiles of this many samples */
     int32_t block_len;        /* block form: time-block length L, 64, 128 or 256; 0 = 128 */
     double long_pole_abs_a;   /* block form: filters with |a_k| above this carry their
                                  block-to-block state in FP64; <= 0 = 0.999 */
     int32_t ckpt_stride;      /* differentiation: samples per checkpoint segment,
                                  a multiple of 128; 0 = 2048 */
-    int32_t queue_wgs;        /* FP32 scan work queue (time_tile 0): resident workgroups
-                                 of four waves per compute unit, 1..8 (capped by what
-                                 fits); 0 = 2 */
+    int32_t balance_wgs;      /* FP32 scan with time_tile -1 or 0: 0 = one wave per filter
+                                 group; 1..8 = balanced static schedule with this many
+                                 resident workgroups (of four waves) per compute unit,
+                                 capped by what fits, used when a packet of max_chunk
+                                 samples and its history fit one LDS window: every wave
+                                 gets an equal share of the work, filter groups being
+                                 cut in time between two waves where needed */
 } spiir_opts;
 
 /* Fill `opts` with defaults: 1 detector, max_chunk 2048, max_delay 0 (from the bank),
- * one peak window per packet, FP32 scan, 4 filters per lane, no time split, L = 128,
- * 0.999, checkpoint stride 2048. */
+ * one peak window per packet, FP32 scan, 4 filters per lane, no time split, no balanced
+ * schedule, L = 128, 0.999, checkpoint stride 2048. */
 void spiir_opts_default(spiir_opts *opts);
 
 /*
@@ -123,10 +124,10 @@ typedef struct {
     int32_t scan_waves;       /* grid of the persistent scan */
     int32_t block_len;
     int32_t n_long_pole;      /* block form: filters carried in FP64 */
-    int32_t scan_wait_timeouts; /* persistent-scan dependency waits that hit their bound
+    int32_t scan_wait_timeouts; /* state hand-off waits (persistent or balanced scan) that hit their bound
                                    (results of those packets are invalid); 0 normally */
-    int32_t queue_wgs;        /* workgroups per detector of the slice work queue; 0 when
-                                 the scan does not use it */
+    int32_t balance_waves;    /* waves per detector of the balanced schedule; 0 when the
+                                 scan does not use it */
 } spiir_bank_info;
 
 /* Fill `info`.  Waits for the bank's last stream (to read the wait-timeout count). */

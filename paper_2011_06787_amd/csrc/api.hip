@@ -136,6 +136,8 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
         return fail(SPIIR_E_UNSUPPORTED, "bank too large for the FP32 scan layout");
     bk.n_slices = (int32_t)slices.size();
     bk.n_slots = slot;
+    bk.h_slice_slots.resize(slices.size());
+    for (size_t si = 0; si < slices.size(); ++si) bk.h_slice_slots[si] = slices[si].n_slots;
     const int64_t lanes = slot * spiir::kWave;
     std::vector<float2> ha(lanes, make_float2(0.f, 0.f)), hb(lanes, make_float2(0.f, 0.f));
     std::vector<int32_t> hd(lanes, 0), hp(lanes, -1);
@@ -164,7 +166,6 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
                         std::max<int64_t>((int64_t)bk.n_det * bk.n_slices * bk.max_chunk, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_queue, 1));
     SPIIR_TRY(dev_alloc(bk, &bk.d_flags, std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 4)));
-    SPIIR_TRY(dev_alloc(bk, &bk.d_slice_head, std::max<int64_t>(2 * (int64_t)bk.n_det, 4)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_order, std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 1)));
     // persistent-scan hand-out order inside a time tile: largest slices first
     std::vector<int32_t> order((size_t)bk.n_det * bk.n_slices);
@@ -192,6 +193,89 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
     return SPIIR_OK;
 }
 
+// Balanced schedule of the FP32 scan: the wrap-around rule for preemptive
+// scheduling on identical machines applied to the slices of one detector.  A slice
+// of m slots costs m + kReduceSlots slot-units of work per packet (the lane
+// reduction of every sub-tile is worth about 0.45 slot).  The wave count W is a
+// whole number c of workgroups on every compute unit (so that every SIMD holds the
+// same number of equal waves), with c as large as allowed while the mean load
+// C = P / W stays at or above the largest slice, so that a cut slice spans only two
+// waves.  Waves are filled in order up to C; a slice that does not fit is cut at
+// the sample fraction that fills the wave: its later part closes this wave's list,
+// its earlier part opens the next wave's list.
+constexpr double kReduceSlots = 0.45;
+
+spiir_status plan_balanced(spiir::Bank &bk, hipStream_t s) {
+    const int32_t S = bk.n_slices;
+    double P = 0.0, pmax = 0.0;
+    for (int32_t i = 0; i < S; ++i) {
+        const double p = bk.h_slice_slots[i] + kReduceSlots;
+        P += p;
+        pmax = std::max(pmax, p);
+    }
+    const int64_t unit = std::max(1, bk.balance_unit);
+    int64_t c = pmax > 0 ? (int64_t)std::floor(P / (pmax * (double)unit)) : 1;
+    c = std::min<int64_t>(c, std::max(1, bk.balance_per_cu));
+    int64_t W = c >= 1 ? c * unit
+                       : std::max<int64_t>(1, pmax > 0 ? (int64_t)std::floor(P / pmax) : 1);
+    // LDS request: the input window, padded so that c workgroups fit on a compute unit
+    // and c + 1 do not; the dispatcher then places exactly c on every compute unit
+    const int64_t cc = std::max<int64_t>(c, 1);
+    const int64_t pad = ((int64_t)spiir::kLdsPerCu * 2 / (2 * cc + 1)) / 512 * 512;
+    bk.balance_lds = (int32_t)std::min<int64_t>(
+        spiir::kLdsPerCu,
+        std::max<int64_t>((int64_t)spiir::scan_fp32_lds_bytes(bk.max_chunk, bk.hist_len), pad));
+    const double C = P / (double)W;
+    std::vector<std::vector<spiir::Seg>> lists((size_t)W);
+    int64_t w = 0;
+    double fill = 0.0;
+    int32_t splits = 0;
+    const double eps = 1e-9 * std::max(1.0, C);
+    for (int32_t i = 0; i < S; ++i) {
+        const double p = bk.h_slice_slots[i] + kReduceSlots;
+        const double room = C - fill;
+        if (w == W - 1 || p <= room + eps) {
+            lists[(size_t)w].push_back(spiir::Seg{i, 0, spiir::kPhiOne, -1});
+            fill += p;
+        } else if (room <= eps) {
+            ++w;
+            lists[(size_t)w].push_back(spiir::Seg{i, 0, spiir::kPhiOne, -1});
+            fill = p;
+        } else {
+            // earlier part (fraction (p - room) / p of the packet) opens wave w+1
+            const int32_t phi = (int32_t)std::min<int64_t>(
+                spiir::kPhiOne - 1,
+                std::max<int64_t>(1, std::llround((p - room) / p * spiir::kPhiOne)));
+            lists[(size_t)w].push_back(spiir::Seg{i, phi, spiir::kPhiOne, splits});
+            ++w;
+            lists[(size_t)w].push_back(spiir::Seg{i, 0, phi, splits});
+            ++splits;
+            fill = p - room;
+        }
+        if (fill >= C - eps && w < W - 1 && i + 1 < S) {
+            ++w;
+            fill = 0.0;
+        }
+    }
+    std::vector<spiir::Seg> segs;
+    std::vector<int32_t> off((size_t)W + 1, 0);
+    for (int64_t k = 0; k < W; ++k) {
+        off[(size_t)k] = (int32_t)segs.size();
+        segs.insert(segs.end(), lists[(size_t)k].begin(), lists[(size_t)k].end());
+    }
+    off[(size_t)W] = (int32_t)segs.size();
+    bk.balance_waves = (int32_t)W;
+    bk.n_splits = splits;
+    SPIIR_TRY(dev_alloc(bk, &bk.d_segs, std::max<int64_t>((int64_t)segs.size(), 1)));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_seg_off, W + 1));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_split_flags, std::max<int64_t>((int64_t)bk.n_det * splits, 4)));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_bqueue, 1));
+    SPIIR_TRY(upload(bk.d_segs, segs, s));
+    SPIIR_TRY(upload(bk.d_seg_off, off, s));
+    SPIIR_HIP(hipStreamSynchronize(s));   // the host vectors die at return
+    return SPIIR_OK;
+}
+
 spiir_status zero_stream_state(spiir::Bank &bk, hipStream_t s) {
     if (bk.mode == SPIIR_MODE_BF16_BLOCK)
         SPIIR_HIP(spiir::launch_zero(bk.d_state64, round16(std::max<int64_t>(bk.n_fpad, 1) * bk.n_det *
@@ -212,9 +296,12 @@ spiir_status zero_queue(spiir::Bank &bk, hipStream_t s) {
     SPIIR_HIP(spiir::launch_zero(bk.d_flags,
                                  round16(std::max<int64_t>((int64_t)bk.n_det * bk.n_slices, 4) *
                                          (int64_t)sizeof(uint32_t)), s));
-    SPIIR_HIP(spiir::launch_zero(bk.d_slice_head,
-                                 round16(std::max<int64_t>(2 * (int64_t)bk.n_det, 4) *
-                                         (int64_t)sizeof(uint32_t)), s));
+    if (bk.balanced) {
+        SPIIR_HIP(spiir::launch_zero(bk.d_bqueue, round16(sizeof(spiir::ScanQueue)), s));
+        SPIIR_HIP(spiir::launch_zero(bk.d_split_flags,
+                                     round16(std::max<int64_t>((int64_t)bk.n_det * bk.n_splits, 4) *
+                                             (int64_t)sizeof(uint32_t)), s));
+    }
     return SPIIR_OK;
 }
 
@@ -235,7 +322,7 @@ void spiir_opts_default(spiir_opts *opts) {
     opts->block_len = 128;
     opts->long_pole_abs_a = 0.999;
     opts->ckpt_stride = 2048;
-    opts->queue_wgs = 2;
+    opts->balance_wgs = 0;
 }
 
 const char *spiir_last_error(void) { return g_error.c_str(); }
@@ -286,8 +373,8 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         if (time_tile != -1 && time_tile != 0 &&
             (time_tile < spiir::kSub || time_tile > 4096 || time_tile % spiir::kSub != 0))
             return fail(SPIIR_E_INVAL, "time_tile must be -1, 0 or a multiple of 16 in [16, 4096]");
-        if (opts.queue_wgs < 0 || opts.queue_wgs > 8)
-            return fail(SPIIR_E_INVAL, "queue_wgs must be in [0, 8]");
+        if (opts.balance_wgs < 0 || opts.balance_wgs > 8)
+            return fail(SPIIR_E_INVAL, "balance_wgs must be in [0, 8]");
         int32_t dmax = 0;
         for (int64_t k = 0; k < F; ++k) {
             const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
@@ -320,8 +407,8 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
         bk.mode = opts.mode;
         bk.fpl = fpl;
         bk.time_tile = time_tile > 0 ? time_tile : 0;
-        bk.queue_per_cu = opts.queue_wgs > 0 ? opts.queue_wgs : 2;
-        bk.slice_queue = time_tile == 0 &&
+        bk.balance_per_cu = opts.balance_wgs;
+        bk.balanced = time_tile <= 0 && opts.balance_wgs > 0 &&
                          (int64_t)bk.max_chunk + hist_len + spiir::kSub <= spiir::kWindowFloats;
         bk.block_len = block_len;
         bk.ckpt_stride = ckpt_stride;
@@ -362,6 +449,7 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
                 if (e != hipSuccess)
                     st = fail(SPIIR_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
             }
+            if (st == SPIIR_OK && bk.balanced) st = plan_balanced(bk, s);
             if (st == SPIIR_OK) st = zero_queue(bk, s);
         }
         if (st == SPIIR_OK) st = zero_stream_state(bk, s);
@@ -461,7 +549,7 @@ spiir_status spiir_bank_get_info(const spiir_bank *h, spiir_bank_info *info) {
     info->filters_per_lane = bk.fpl;
     info->time_tile = bk.time_tile;
     info->scan_waves = bk.scan_waves;
-    info->queue_wgs = bk.slice_queue ? bk.queue_wgs : 0;
+    info->balance_waves = bk.balanced ? bk.balance_waves : 0;
     info->block_len = bk.block_len;
     info->n_long_pole = bk.n_long_pole;
     if (bk.d_queue != nullptr) {
@@ -469,6 +557,12 @@ spiir_status spiir_bank_get_info(const spiir_bank *h, spiir_bank_info *info) {
         SPIIR_HIP(hipStreamSynchronize(bk.last_stream));
         SPIIR_HIP(hipMemcpy(&q, bk.d_queue, sizeof(q), hipMemcpyDeviceToHost));
         info->scan_wait_timeouts = (int32_t)q.error;
+    }
+    if (bk.d_bqueue != nullptr) {
+        spiir::ScanQueue q{};
+        SPIIR_HIP(hipStreamSynchronize(bk.last_stream));
+        SPIIR_HIP(hipMemcpy(&q, bk.d_bqueue, sizeof(q), hipMemcpyDeviceToHost));
+        info->scan_wait_timeouts += (int32_t)q.error;
     }
     return SPIIR_OK;
 }

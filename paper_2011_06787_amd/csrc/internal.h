@@ -16,6 +16,7 @@ constexpr int kSub = 16;           // samples per register sub-tile of the FP32 
 constexpr int kScanWaves = 4;      // waves per workgroup of the FP32 scan
 constexpr int kMaxDelay = 8191;    // largest supported delay (samples)
 constexpr int kWindowFloats = 12288;  // LDS input window of the FP32 scan (floats)
+constexpr int kLdsPerCu = 160 * 1024;  // LDS of one compute unit (bytes)
 
 // Device bookkeeping of the persistent FP32 scan (one per bank).
 struct ScanQueue {
@@ -56,6 +57,19 @@ struct Slice {
     int32_t pad;
 };
 
+// Balanced FP32-scan schedule: one entry of a wave's work list, the slice's samples
+// [phi0 n, phi1 n) with phi in units of 1/65536 of the packet (rounded down to whole
+// sub-tiles in the kernel).  A slice cut between two waves has phi1 < 65536 on the
+// wave that runs its first part (at the start of that wave's list) and phi0 > 0 on
+// the wave that continues it (at the end of its list); `flag` indexes their hand-off.
+struct Seg {
+    int32_t slice;
+    int32_t phi0;
+    int32_t phi1;
+    int32_t flag;   // -1 when the slice is not cut
+};
+constexpr int32_t kPhiOne = 65536;
+
 struct Bank {
     // shape
     int32_t n_templates = 0;
@@ -71,9 +85,12 @@ struct Bank {
     int32_t scan_tile = 2048;  // samples per LDS input window of the one-shot FP32 scan
     int32_t time_tile = 256;   // samples per work item of the persistent scan; 0 = one-shot
     int32_t scan_waves = 0;    // resident waves of the persistent scan (grid size)
-    bool slice_queue = false;  // one-shot scan hands slices out through a work queue
-    int32_t queue_per_cu = 2;  // requested resident workgroups per compute unit (slice queue)
-    int32_t queue_wgs = 0;     // workgroups per detector of the slice-queue scan
+    bool balanced = false;     // one-shot scan runs the balanced static schedule
+    int32_t balance_per_cu = 0;  // requested resident workgroups per compute unit
+    int32_t balance_unit = 0;    // waves per detector with one workgroup per compute unit
+    int32_t balance_waves = 0;   // waves per detector of the balanced schedule
+    int32_t balance_lds = 0;     // dynamic LDS per workgroup of the balanced scan (bytes)
+    int32_t n_splits = 0;        // slices cut between two waves (per detector)
     int32_t ckpt_stride = 2048;  // differentiation: samples per checkpoint segment
 
     // FP32 scan layout
@@ -90,7 +107,11 @@ struct Bank {
     float2 *d_partial = nullptr; // [D][n_slices][max_chunk]
     ScanQueue *d_queue = nullptr;
     uint32_t *d_flags = nullptr; // [D][n_slices]: tiles completed (epoch-relative)
-    uint32_t *d_slice_head = nullptr;  // [2][D]: slice-queue head and finished waves per detector
+    Seg *d_segs = nullptr;             // balanced schedule: work lists of all waves
+    int32_t *d_seg_off = nullptr;      // [balance_waves+1]: list of wave w is [off[w], off[w+1])
+    uint32_t *d_split_flags = nullptr; // [D][n_splits]: launches whose first part has published
+    ScanQueue *d_bqueue = nullptr;     // balanced schedule: launch epoch, finished waves, timeouts
+    std::vector<int32_t> h_slice_slots;  // slots of every slice (host copy, for planning)
     int32_t *d_order = nullptr;  // [D*n_slices]: det*n_slices + slice, largest slices first
     int32_t *d_slice_order = nullptr;  // [n_slices]: slices, largest first
 

@@ -10,19 +10,20 @@
 // which covers every delay: filter k at sample n reads window[n - n0 + hist_len - d_k].
 // Time advances in register sub-tiles of kSub samples.  Each lane accumulates
 // the sum of its own filters per sample; the 64 lane partials of a sub-tile are
-// then reduced through a padded LDS transpose (each lane sums 16 rows of one
-// sample) and two cross-half shuffles, and 16 lanes write the slice's partial
-// template sum for the sub-tile.  A second kernel adds the slices of each template.
+// then reduced in registers by a transpose-reduce across lanes (lane-half swaps,
+// then row rotations and mirrors within 16-lane rows): every step halves the
+// samples a lane holds and doubles the lanes summed, so 16 lanes end with the
+// slice's partial template sum of one sample each.  No LDS is used for it.  A
+// second kernel adds the slices of each template.
 //
 // Arithmetic per filter-sample: 2 mul + 4 fma (complex a*y + b*x with real x)
 // and 2 adds into the lane sum (none for a lane's first filter): at most 8 VALU
 // lane-operations for the paper's 12 flops.
 //
 // Schedules.  The static kernel gives one slice to each wave.  When the packet and
-// its history fit one LDS window, the slice-queue kernel instead keeps a fixed
-// number of workgroups resident and lets every wave take the next slice (largest
-// first) from a per-detector counter until none is left, so the compute units
-// finish together however the slice count divides over them.
+// its history fit one LDS window, the balanced kernel (on request) instead runs a
+// fixed set of resident waves, each with a host-planned list of equal total work in
+// which slices may be cut in time between two waves.
 #include <algorithm>
 
 #include "internal.h"
@@ -30,8 +31,74 @@
 namespace spiir {
 namespace {
 
-constexpr int kRedStride = kSub + 1;  // float2 per lane row, padded against bank conflicts
-static_assert(kSub == 16, "the lane reduction assumes 4 quarters of 16 lanes");
+static_assert(kSub == 16, "the lane reduction halves 16 samples four times");
+
+// Cross-lane data movement for the reduction.  DPP controls (within rows of 16
+// lanes): rotate by 8 (partner l^8), mirror within 8 lanes (partner 7-i), and
+// quad permutations swapping neighbours at distance 1 and 2.
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// a in the lower, b in the upper half-wave exchanged: every lane gets the sum of one
+// of the two values over itself and its partner in the other half
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// the same between the two 16-lane rows of each half-wave
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sample of the sub-tile whose 64-lane total reduce_lanes leaves in this lane: the
+// two swap steps are traced on the sample offsets they select (8 and 4), the two
+// DPP steps select by lane bits 3 and 2.
+__device__ __forceinline__ int reduce_sample(int lane) {
+    const auto h8 = __builtin_amdgcn_permlane32_swap(0u, 8u, false, false);
+    const auto h4 = __builtin_amdgcn_permlane16_swap(0u, 4u, false, false);
+    return (int)h8[0] + (int)h4[0] + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+}
+
+// Sum acc[s] over the 64 lanes for all 16 samples s; the lane receives the total of
+// sample reduce_sample(lane) (all four lanes of a quad hold the same one).
+__device__ __forceinline__ float2 reduce_lanes(const float2 (&acc)[kSub], int lane) {
+    float2 w[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        w[s] = make_float2(swap32_sum(acc[s].x, acc[s + 8].x), swap32_sum(acc[s].y, acc[s + 8].y));
+    float2 u[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        u[s] = make_float2(swap16_sum(w[s].x, w[s + 4].x), swap16_sum(w[s].y, w[s + 4].y));
+    const bool b3 = (lane & 8) != 0;
+    float2 t[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const float2 send = b3 ? u[s] : u[s + 2];
+        const float2 keep = b3 ? u[s + 2] : u[s];
+        t[s] = make_float2(keep.x + dpp_move<kDppRowRor8>(send.x),
+                           keep.y + dpp_move<kDppRowRor8>(send.y));
+    }
+    const bool b2 = (lane & 4) != 0;
+    const float2 send = b2 ? t[0] : t[1];
+    const float2 keep = b2 ? t[1] : t[0];
+    float2 v = make_float2(keep.x + dpp_move<kDppRowHalfMirror>(send.x),
+                           keep.y + dpp_move<kDppRowHalfMirror>(send.y));
+    v.x += dpp_move<kDppQuadXor1>(v.x);
+    v.y += dpp_move<kDppQuadXor1>(v.y);
+    v.x += dpp_move<kDppQuadXor2>(v.x);
+    v.y += dpp_move<kDppQuadXor2>(v.y);
+    return v;
+}
 
 __device__ __forceinline__ void lds_fence() {
     // orders this wave's LDS writes before its later LDS reads (and vice versa)
@@ -65,29 +132,40 @@ __device__ __forceinline__ void load_window(float *__restrict__ win, const float
     }
 }
 
-template <int MAXM, bool TAIL>
-__device__ __forceinline__ void sub_tile(const float *__restrict__ win, float2 *__restrict__ red,
-                                         int lane, int m, int s0, int valid,
-                                         const float (&ar)[MAXM], const float (&ai)[MAXM],
-                                         const float (&br)[MAXM], const float (&bi)[MAXM],
-                                         const int (&base)[MAXM], float (&yr)[MAXM],
-                                         float (&yi)[MAXM], float2 *__restrict__ out) {
-    // every caller has m >= 1: in a full sub-tile the lane sums start from the first
+template <int MAXM, int M, bool TAIL>
+__device__ __forceinline__ void sub_tile_m(const float *__restrict__ win, int red_sample,
+                                           int lane, int s0, int valid,
+                                           const float (&ar)[MAXM], const float (&ai)[MAXM],
+                                           const float (&br)[MAXM], const float (&bi)[MAXM],
+                                           const int (&base)[MAXM], float (&yr)[MAXM],
+                                           float (&yi)[MAXM], float2 *__restrict__ out) {
+    // M >= 1 filters per lane: in a full sub-tile the lane sums start from the first
     // filter's outputs (no zero fill, no first add)
     float2 acc[kSub];
     if (TAIL) {
 #pragma unroll
         for (int s = 0; s < kSub; ++s) acc[s] = make_float2(0.0f, 0.0f);
     }
+    // The kSub inputs of filter j+1 are read from LDS while filter j computes, so a
+    // wave waits for LDS once per sub-tile instead of once per pair of samples (the
+    // scheduling barriers keep the compiler from sinking the reads next to their
+    // uses).  Reads past `valid` in a tail stay inside the window's kSub padding.
+    float xb[2][kSub];   // filter j reads xb[j & 1] (a compile-time index: no copies)
 #pragma unroll
-    for (int j = 0; j < MAXM; ++j) {
-        if (j == 0 || j < m) {  // wave-uniform
-            const float *xp = win + base[j] + s0;
+    for (int s = 0; s < kSub; ++s) xb[0][s] = win[base[0] + s0 + s];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        {
+            if (j + 1 < M) {
+#pragma unroll
+                for (int s = 0; s < kSub; ++s) xb[(j + 1) & 1][s] = win[base[j + 1] + s0 + s];
+            }
+            __builtin_amdgcn_sched_barrier(0);
             float r = yr[j], im = yi[j];
 #pragma unroll
             for (int s = 0; s < kSub; ++s) {
                 if (!TAIL || s < valid) {
-                    const float xv = xp[s];
+                    const float xv = xb[j & 1][s];
                     const float nr = fmaf(ar[j], r, fmaf(-ai[j], im, br[j] * xv));
                     const float ni = fmaf(ar[j], im, fmaf(ai[j], r, bi[j] * xv));
                     r = nr;
@@ -102,27 +180,40 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, float2 *
             }
             yr[j] = r;
             yi[j] = im;
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
-    // lane -> sample transpose: row `lane` holds this lane's kSub partial sums
-#pragma unroll
-    for (int s = 0; s < kSub; ++s) red[lane * kRedStride + s] = acc[s];
-    lds_fence();
-    const int q = lane >> 4;     // quarter of the wave: rows 16q .. 16q+15
-    const int s = lane & 15;     // sample of the sub-tile this lane reduces
-    float vr = 0.0f, vi = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const float2 v = red[(q * 16 + i) * kRedStride + s];
-        vr += v.x;
-        vi += v.y;
+    const float2 v = reduce_lanes(acc, lane);
+    if ((lane & 3) == 0 && (!TAIL || red_sample < valid)) out[red_sample] = v;
+}
+
+// One sub-tile for a wave whose slice has m (1..MAXM, wave-uniform) filters per lane:
+// a scalar branch to the variant compiled for exactly m.
+template <int MAXM, bool TAIL>
+__device__ __forceinline__ void sub_tile(const float *__restrict__ win, int red_sample, int lane,
+                                         int m, int s0, int valid, const float (&ar)[MAXM],
+                                         const float (&ai)[MAXM], const float (&br)[MAXM],
+                                         const float (&bi)[MAXM], const int (&base)[MAXM],
+                                         float (&yr)[MAXM], float (&yi)[MAXM],
+                                         float2 *__restrict__ out) {
+#define SPIIR_SUB_TILE(M)                                                                    \
+    case M:                                                                                  \
+        if constexpr (M <= MAXM)                                                             \
+            sub_tile_m<MAXM, M, TAIL>(win, red_sample, lane, s0, valid, ar, ai, br, bi, base, yr, \
+                                      yi, out);                                              \
+        break;
+    switch (m) {
+        SPIIR_SUB_TILE(1)
+        SPIIR_SUB_TILE(2)
+        SPIIR_SUB_TILE(3)
+        SPIIR_SUB_TILE(4)
+        SPIIR_SUB_TILE(5)
+        SPIIR_SUB_TILE(6)
+        SPIIR_SUB_TILE(7)
+        SPIIR_SUB_TILE(8)
+    default: break;
     }
-    lds_fence();
-    vr += __shfl_xor(vr, 16);
-    vi += __shfl_xor(vi, 16);
-    vr += __shfl_xor(vr, 32);
-    vi += __shfl_xor(vi, 32);
-    if (lane < kSub && (!TAIL || lane < valid)) out[lane] = make_float2(vr, vi);
+#undef SPIIR_SUB_TILE
 }
 
 template <int MAXM>
@@ -139,7 +230,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     // per-slot tests below are scalar branches
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    float2 *red = reinterpret_cast<float2 *>(smem + win_floats) + wave * kWave * kRedStride;
+    const int red_sample = reduce_sample(lane);
     const int det = blockIdx.y;
     // slices go out largest first, so the waves of a workgroup carry equal work
     const int rank = blockIdx.x * kScanWaves + wave;
@@ -185,7 +276,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
         if (!active) continue;
         int s0 = 0;
         for (; s0 + kSub <= T; s0 += kSub) {
-            sub_tile<MAXM, false>(win, red, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
+            sub_tile<MAXM, false>(win, red_sample, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
                                   pout + n0 + s0);
             const int e = n0 + s0 + kSub;
             if (ck != nullptr && e % ckpt_stride == 0 && e < n) {
@@ -196,7 +287,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
             }
         }
         if (s0 < T)
-            sub_tile<MAXM, true>(win, red, lane, m, s0, T - s0, ar, ai, br, bi, base, yr, yi,
+            sub_tile<MAXM, true>(win, red_sample, lane, m, s0, T - s0, ar, ai, br, bi, base, yr, yi,
                                  pout + n0 + s0);
     }
     if (active) {
@@ -206,108 +297,11 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     }
 }
 
-// Slice-queue variant of the one-shot scan: the window x[-hist_len, n) of the
-// workgroup's detector is loaded once, then every wave repeatedly takes the next
-// slice from head[det] (slices largest first) and walks the whole packet for it.
-// done[det] counts the waves that found the queue empty; the last of them rewinds
-// both counters for the next launch (kernel boundaries order that with it).
-template <int MAXM>
-__global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_queue_kernel(
-    const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
-    float2 *__restrict__ state, const Slice *__restrict__ slices,
-    const int32_t *__restrict__ slice_order, int32_t n_slices, int32_t n_det,
-    int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
-    int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, int32_t win_floats,
-    float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg, uint32_t *__restrict__ head) {
-    extern __shared__ float smem[];
-    float *win = smem;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lane = threadIdx.x % kWave;
-    float2 *red = reinterpret_cast<float2 *>(smem + win_floats) + wave * kWave * kRedStride;
-    const int det = blockIdx.y;
-    const float *xd = x + (int64_t)det * n;
-    const float *hd = hist + (int64_t)det * hist_len;
-    load_window(win, xd, hd, hist_len, 0, n, threadIdx.x, blockDim.x);
-    __syncthreads();
-    float2 *st = state + (int64_t)det * lanes_total;
-    float2 *ck = ckpt != nullptr ? ckpt + (int64_t)det * n_seg * lanes_total : nullptr;
-    for (;;) {
-        uint32_t r = 0;
-        if (lane == 0)
-            r = __hip_atomic_fetch_add(head + det, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        r = __builtin_amdgcn_readfirstlane(r);
-        if (r >= (uint32_t)n_slices) break;
-        const int sidx = __builtin_amdgcn_readfirstlane(slice_order[r]);
-        Slice sl = slices[sidx];
-        sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
-        sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
-        const int m = sl.n_slots;
-        float ar[MAXM], ai[MAXM], br[MAXM], bi[MAXM], yr[MAXM], yi[MAXM];
-        int base[MAXM];
-#pragma unroll
-        for (int j = 0; j < MAXM; ++j) {
-            if (j < m) {
-                const int64_t g = (int64_t)(sl.slot_base + j) * kWave + lane;
-                const float2 a = ca[g], b = cb[g], y = st[g];
-                ar[j] = a.x; ai[j] = a.y; br[j] = b.x; bi[j] = b.y; yr[j] = y.x; yi[j] = y.y;
-                base[j] = hist_len - cd[g];
-            } else {
-                ar[j] = ai[j] = br[j] = bi[j] = yr[j] = yi[j] = 0.0f;
-                base[j] = 0;
-            }
-        }
-        if (ck != nullptr) {
-#pragma unroll
-            for (int j = 0; j < MAXM; ++j)
-                if (j < m) ck[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
-        }
-        float2 *pout = partial + ((int64_t)det * n_slices + sidx) * part_stride;
-        int s0 = 0;
-        for (; s0 + kSub <= n; s0 += kSub) {
-            sub_tile<MAXM, false>(win, red, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
-                                  pout + s0);
-            const int e = s0 + kSub;
-            if (ck != nullptr && e % ckpt_stride == 0 && e < n) {
-                float2 *cs = ck + (int64_t)(e / ckpt_stride) * lanes_total;
-#pragma unroll
-                for (int j = 0; j < MAXM; ++j)
-                    if (j < m) cs[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
-            }
-        }
-        if (s0 < n)
-            sub_tile<MAXM, true>(win, red, lane, m, s0, n - s0, ar, ai, br, bi, base, yr, yi,
-                                 pout + s0);
-#pragma unroll
-        for (int j = 0; j < MAXM; ++j)
-            if (j < m) st[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
-    }
-    if (lane == 0) {
-        uint32_t *done = head + n_det;
-        const uint32_t old =
-            __hip_atomic_fetch_add(done + det, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == gridDim.x * kScanWaves - 1) {
-            __hip_atomic_store(head + det, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(done + det, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-// Persistent variant.  The packet is cut into time tiles of `tile` samples and
-// the work items are (detector, slice, tile), handed out in tile-major order
-// (largest slices first inside a tile) by an atomic counter, one item per wave at
-// a time, so every SIMD gets an equal share however uneven the slices are.  An
-// item needs the state its slice reached at the end of the previous tile, which
-// another wave, possibly on another XCD, produced.  The hand-off avoids cache-wide
-// operations: the carried state is written and read with device-scope atomic
-// accesses (coherent across XCDs, not kept in the non-coherent caches); the
-// producer waits for those stores to complete before it advances the slice's flag
-// (a device-scope atomic), and the consumer spins on the flag before it loads the
-// state.  Items are handed out in order, so the producer of any awaited item is
-// already running and the wait ends; it is bounded all the same, and a wait that
-// hits the bound is counted in ScanQueue::error.  Flags count tiles since the bank
-// was created: a launch knows the count every slice reached before it (`epoch`),
-// and the last wave to finish advances the epoch and rewinds the counters for the
-// next launch (kernel boundaries order these with the next launch).
+// Cross-XCD hand-off of filter state inside one launch.  The state travels through
+// device-scope atomic accesses (coherent across XCDs, not held in the non-coherent
+// caches); the producer waits until those stores have completed before it moves
+// the flag (a device-scope atomic), and the consumer spins on the flag before it
+// loads the state.  The wait is bounded; a wait that hits the bound is counted.
 constexpr uint32_t kSpinLimit = 1u << 22;
 
 __device__ __forceinline__ float2 load_coherent(const float2 *p) {
@@ -330,6 +324,171 @@ __device__ __forceinline__ void wait_memory() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 
+// Wait until *flag has reached `target` (counts are compared modulo 2^32); lane 0
+// polls, the other lanes wait at the following wave-wide operations.
+__device__ __forceinline__ void wait_flag(const uint32_t *flag, uint32_t target, int lane,
+                                          uint32_t *error) {
+    if (lane == 0) {
+        uint32_t spins = 0;
+        while ((int32_t)(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                         target) < 0) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins == kSpinLimit) {
+                __hip_atomic_fetch_add(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    wait_memory();
+}
+
+// First sample of the sub-tile that starts at fraction phi of a packet of n samples.
+__device__ __forceinline__ int phi_sample(int32_t phi, int32_t n) {
+    if (phi >= kPhiOne) return n;
+    const int t = (int)(((int64_t)phi * n + kPhiOne / 2) >> 16);
+    return min(n, t) & ~(kSub - 1);
+}
+
+// Balanced static schedule of the one-shot scan.  The host cuts the detector's
+// slices into equal shares of work, one per resident wave (the wrap-around rule
+// for preemptive scheduling on identical machines: fill wave after wave up to the
+// mean load; a slice that does not fit is cut in time, its later part closing the
+// current wave's list and its earlier part opening the next one).  Every SIMD then
+// carries the same load whatever the slice sizes, and the earlier part of a cut
+// slice runs first in its wave while the later part runs last in its own, so the
+// state hand-off between them rarely waits.  The window x[-hist_len, n) of the
+// workgroup's detector is loaded into LDS once for all its waves.
+template <int MAXM>
+__global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
+    const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
+    float2 *__restrict__ state, const Slice *__restrict__ slices, int32_t n_slices,
+    const Seg *__restrict__ segs, const int32_t *__restrict__ seg_off, int32_t waves_per_det,
+    int32_t n_splits, uint32_t *__restrict__ flags, ScanQueue *__restrict__ queue,
+    int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
+    int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, float2 *__restrict__ ckpt,
+    int32_t ckpt_stride, int32_t n_seg) {
+    extern __shared__ float smem[];
+    float *win = smem;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int red_sample = reduce_sample(lane);
+    const int det = blockIdx.y;
+    const uint32_t epoch =
+        __hip_atomic_load(&queue->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const float *xd = x + (int64_t)det * n;
+    const float *hd = hist + (int64_t)det * hist_len;
+    load_window(win, xd, hd, hist_len, 0, n, threadIdx.x, blockDim.x);
+    __syncthreads();
+    float2 *st = state + (int64_t)det * lanes_total;
+    float2 *ck = ckpt != nullptr ? ckpt + (int64_t)det * n_seg * lanes_total : nullptr;
+    uint32_t *fl = flags + (int64_t)det * n_splits;
+    const int w = blockIdx.x * kScanWaves + wave;
+    const int e0 = w < waves_per_det ? __builtin_amdgcn_readfirstlane(seg_off[w]) : 0;
+    const int e1 = w < waves_per_det ? __builtin_amdgcn_readfirstlane(seg_off[w + 1]) : 0;
+    for (int e = e0; e < e1; ++e) {
+        Seg sg = segs[e];
+        sg.slice = __builtin_amdgcn_readfirstlane(sg.slice);
+        sg.phi0 = __builtin_amdgcn_readfirstlane(sg.phi0);
+        sg.phi1 = __builtin_amdgcn_readfirstlane(sg.phi1);
+        sg.flag = __builtin_amdgcn_readfirstlane(sg.flag);
+        Slice sl = slices[sg.slice];
+        sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
+        sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
+        const int m = sl.n_slots;
+        const int t0 = sg.phi0 > 0 ? phi_sample(sg.phi0, n) : 0;
+        const int t1 = phi_sample(sg.phi1, n);
+        float ar[MAXM], ai[MAXM], br[MAXM], bi[MAXM], yr[MAXM], yi[MAXM];
+        int base[MAXM];
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+            if (j < m) {
+                const int64_t g = (int64_t)(sl.slot_base + j) * kWave + lane;
+                const float2 a = ca[g], b = cb[g];
+                ar[j] = a.x; ai[j] = a.y; br[j] = b.x; bi[j] = b.y;
+                base[j] = hist_len - cd[g];
+            } else {
+                ar[j] = ai[j] = br[j] = bi[j] = 0.0f;
+                base[j] = 0;
+            }
+        }
+        if (sg.phi0 > 0) wait_flag(fl + sg.flag, epoch + 1u, lane, &queue->error);
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+            if (j < m) {
+                const int64_t g = (int64_t)(sl.slot_base + j) * kWave + lane;
+                const float2 y = sg.phi0 > 0 ? load_coherent(st + g) : st[g];
+                yr[j] = y.x; yi[j] = y.y;
+            } else {
+                yr[j] = yi[j] = 0.0f;
+            }
+        }
+        if (ck != nullptr && t0 == 0) {
+#pragma unroll
+            for (int j = 0; j < MAXM; ++j)
+                if (j < m) ck[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+        }
+        float2 *pout = partial + ((int64_t)det * n_slices + sg.slice) * part_stride;
+        const int full_end = t1 == n ? (n & ~(kSub - 1)) : t1;
+        for (int s0 = t0; s0 < full_end; s0 += kSub) {
+            sub_tile<MAXM, false>(win, red_sample, lane, m, s0, kSub, ar, ai, br, bi, base, yr,
+                                  yi, pout + s0);
+            const int eo = s0 + kSub;
+            if (ck != nullptr && eo % ckpt_stride == 0 && eo < n) {
+                float2 *cs = ck + (int64_t)(eo / ckpt_stride) * lanes_total;
+#pragma unroll
+                for (int j = 0; j < MAXM; ++j)
+                    if (j < m) cs[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+            }
+        }
+        if (t1 == n && full_end < n)
+            sub_tile<MAXM, true>(win, red_sample, lane, m, full_end, n - full_end, ar, ai, br, bi,
+                                 base, yr, yi, pout + full_end);
+        if (sg.phi1 < kPhiOne) {
+            // first part of a cut slice: publish the state for the wave that continues it
+#pragma unroll
+            for (int j = 0; j < MAXM; ++j)
+                if (j < m)
+                    store_coherent(st + (int64_t)(sl.slot_base + j) * kWave + lane,
+                                   make_float2(yr[j], yi[j]));
+            wait_memory();
+            if (lane == 0)
+                __hip_atomic_store(fl + sg.flag, epoch + 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+#pragma unroll
+            for (int j = 0; j < MAXM; ++j)
+                if (j < m) st[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+        }
+    }
+    // the last wave to finish advances the epoch for the next launch
+    if (lane == 0) {
+        const uint32_t total = gridDim.x * gridDim.y * kScanWaves;
+        const uint32_t old =
+            __hip_atomic_fetch_add(&queue->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == total - 1) {
+            __hip_atomic_store(&queue->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&queue->epoch, epoch + 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Persistent variant.  The packet is cut into time tiles of `tile` samples and
+// the work items are (detector, slice, tile), handed out in tile-major order
+// (largest slices first inside a tile) by an atomic counter, one item per wave at
+// a time, so every SIMD gets an equal share however uneven the slices are.  An
+// item needs the state its slice reached at the end of the previous tile, which
+// another wave, possibly on another XCD, produced.  The hand-off avoids cache-wide
+// operations: the carried state is written and read with device-scope atomic
+// accesses (coherent across XCDs, not kept in the non-coherent caches); the
+// producer waits for those stores to complete before it advances the slice's flag
+// (a device-scope atomic), and the consumer spins on the flag before it loads the
+// state.  Items are handed out in order, so the producer of any awaited item is
+// already running and the wait ends; it is bounded all the same, and a wait that
+// hits the bound is counted in ScanQueue::error.  Flags count tiles since the bank
+// was created: a launch knows the count every slice reached before it (`epoch`),
+// and the last wave to finish advances the epoch and rewinds the counters for the
+// next launch (kernel boundaries order these with the next launch).
 template <int MAXM>
 __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
     const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
@@ -340,8 +499,8 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
     uint32_t *__restrict__ flags) {
     extern __shared__ float smem[];
     float *win = smem;
-    float2 *red = reinterpret_cast<float2 *>(smem + win_floats);
     const int lane = threadIdx.x;
+    const int red_sample = reduce_sample(lane);
     const uint32_t per_round = (uint32_t)n_det * (uint32_t)n_slices;
     const uint32_t n_tiles = (uint32_t)((n + tile - 1) / tile);
     const uint32_t total = n_tiles * per_round;
@@ -415,10 +574,10 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
         float2 *pout = partial + ((int64_t)det * n_slices + sidx) * part_stride + n0;
         int s0 = 0;
         for (; s0 + kSub <= T; s0 += kSub)
-            sub_tile<MAXM, false>(win, red, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
+            sub_tile<MAXM, false>(win, red_sample, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
                                   pout + s0);
         if (s0 < T)
-            sub_tile<MAXM, true>(win, red, lane, m, s0, T - s0, ar, ai, br, bi, base, yr, yi,
+            sub_tile<MAXM, true>(win, red_sample, lane, m, s0, T - s0, ar, ai, br, bi, base, yr, yi,
                                  pout + s0);
 #pragma unroll
         for (int j = 0; j < MAXM; ++j)
@@ -448,13 +607,11 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
 
 size_t scan_fp32_lds_bytes(int32_t tile, int32_t hist_len) {
     const int32_t win_floats = ((tile + hist_len + kSub) + 3) & ~3;
-    return (size_t)win_floats * sizeof(float) +
-           (size_t)kScanWaves * kWave * kRedStride * sizeof(float2);
+    return (size_t)win_floats * sizeof(float);
 }
 
 size_t scan_persistent_lds_bytes(int32_t tile, int32_t hist_len) {
-    const int32_t win_floats = ((tile + hist_len + kSub) + 3) & ~3;
-    return (size_t)win_floats * sizeof(float) + (size_t)kWave * kRedStride * sizeof(float2);
+    return scan_fp32_lds_bytes(tile, hist_len);
 }
 
 namespace {
@@ -472,21 +629,24 @@ hipError_t prepare_fpl(Bank &bk) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)scan_fp32_lds_bytes(bk.scan_tile, bk.hist_len));
     if (e != hipSuccess) return e;
-    if (bk.slice_queue) {
-        // resident workgroups: queue_wgs per compute unit (at most what fits), shared
-        // out over the detectors
+    if (bk.balanced) {
+        // the launch may pad its LDS request up to the whole LDS of a compute unit (so
+        // that exactly the planned number of workgroups fits on each)
         const int lds = (int)scan_fp32_lds_bytes(bk.max_chunk, bk.hist_len);
-        e = hipFuncSetAttribute((const void *)scan_fp32_queue_kernel<MAXM>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        e = hipFuncSetAttribute((const void *)scan_fp32_balanced_kernel<MAXM>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsPerCu);
         if (e != hipSuccess) return e;
         int per_cu = 0, cus = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, (const void *)scan_fp32_queue_kernel<MAXM>, kWave * kScanWaves, lds);
+            &per_cu, (const void *)scan_fp32_balanced_kernel<MAXM>, kWave * kScanWaves, lds);
         if (e != hipSuccess) return e;
         e = device_cus(cus);
         if (e != hipSuccess) return e;
-        const int64_t want = (int64_t)std::max(1, std::min(bk.queue_per_cu, per_cu)) * std::max(1, cus);
-        bk.queue_wgs = (int32_t)std::max<int64_t>(1, (want + bk.n_det - 1) / bk.n_det);
+        // planner inputs: waves per detector with one workgroup on every compute unit,
+        // and the most workgroups per compute unit allowed
+        bk.balance_unit = (int32_t)std::max<int64_t>(1, (int64_t)std::max(1, cus) / bk.n_det) *
+                          kScanWaves;
+        bk.balance_per_cu = std::max(1, std::min(bk.balance_per_cu, per_cu));
     }
     if (bk.time_tile <= 0) return hipSuccess;
     const int lds = (int)scan_persistent_lds_bytes(bk.time_tile, bk.hist_len);
@@ -516,16 +676,14 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            bk.d_delay, bk.d_state, bk.d_slices, bk.d_order, bk.n_slices, bk.n_det,
                            lanes, x, n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk,
                            bk.time_tile, win_floats, bk.d_queue, bk.d_flags);
-    } else if (bk.slice_queue) {
-        const int32_t win_floats = ((n + bk.hist_len + kSub) + 3) & ~3;
-        const int64_t need = (bk.n_slices + kScanWaves - 1) / kScanWaves;
-        const dim3 grid((unsigned)std::min<int64_t>(bk.queue_wgs, need), bk.n_det);
-        hipLaunchKernelGGL(scan_fp32_queue_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
-                           scan_fp32_lds_bytes(n, bk.hist_len), s, bk.d_a, bk.d_b, bk.d_delay,
-                           bk.d_state, bk.d_slices, bk.d_slice_order, bk.n_slices, bk.n_det, lanes,
-                           x, n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk, win_floats,
-                           ckpt, bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride,
-                           bk.d_slice_head);
+    } else if (bk.balanced) {
+        const dim3 grid((unsigned)((bk.balance_waves + kScanWaves - 1) / kScanWaves), bk.n_det);
+        hipLaunchKernelGGL(scan_fp32_balanced_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
+                           (size_t)bk.balance_lds, s, bk.d_a, bk.d_b, bk.d_delay,
+                           bk.d_state, bk.d_slices, bk.n_slices, bk.d_segs, bk.d_seg_off,
+                           bk.balance_waves, bk.n_splits, bk.d_split_flags, bk.d_bqueue, lanes, x,
+                           n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk, ckpt,
+                           bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride);
     } else {
         const int32_t tile = bk.scan_tile;
         const int32_t win_floats = ((tile + bk.hist_len + kSub) + 3) & ~3;

@@ -52,7 +52,7 @@ class Opts(ctypes.Structure):
         ("block_len", ctypes.c_int32),
         ("long_pole_abs_a", ctypes.c_double),
         ("ckpt_stride", ctypes.c_int32),
-        ("queue_wgs", ctypes.c_int32),
+        ("balance_wgs", ctypes.c_int32),
     ]
 
 
@@ -65,7 +65,7 @@ class BankInfo(ctypes.Structure):
         ("n_slices", ctypes.c_int32), ("filters_per_lane", ctypes.c_int32),
         ("time_tile", ctypes.c_int32), ("scan_waves", ctypes.c_int32),
         ("block_len", ctypes.c_int32), ("n_long_pole", ctypes.c_int32),
-        ("scan_wait_timeouts", ctypes.c_int32), ("queue_wgs", ctypes.c_int32),
+        ("scan_wait_timeouts", ctypes.c_int32), ("balance_waves", ctypes.c_int32),
     ]
 
 
@@ -148,7 +148,7 @@ class SpiirBank:
     def __init__(self, offsets, a, b, delay, *, n_detectors: int = 1, max_chunk: int = 2048,
                  max_delay: int = 0, peak_window: int = 0, mode: int = MODE_FP32_SCAN,
                  filters_per_lane: int = 0, time_tile: int = 0, block_len: int = 0,
-                 long_pole_abs_a: float = 0.999, ckpt_stride: int = 0, queue_wgs: int = 0,
+                 long_pole_abs_a: float = 0.999, ckpt_stride: int = 0, balance_wgs: int = 0,
                  stream=None):
         lib = load()
         self._offsets = np.ascontiguousarray(offsets, dtype=np.int32)
@@ -159,7 +159,7 @@ class SpiirBank:
         o.n_detectors, o.max_chunk, o.max_delay = n_detectors, max_chunk, max_delay
         o.peak_window, o.mode, o.filters_per_lane = peak_window, mode, filters_per_lane
         o.time_tile, o.block_len, o.long_pole_abs_a = time_tile, block_len, long_pole_abs_a
-        o.ckpt_stride, o.queue_wgs = ckpt_stride, queue_wgs
+        o.ckpt_stride, o.balance_wgs = ckpt_stride, balance_wgs
         self.opts = o
         h = _P()
         st = lib.spiir_bank_create(int(self._offsets.shape[0] - 1),

@@ -69,8 +69,8 @@ GOOD = dict(offsets=[0, 2], a=[0.5 + 0.1j, 0.9j], b=[1 + 0j, 0.5j], d=[0, 3])
     (dict(filters_per_lane=3), spiir.SPIIR_E_INVAL),
     (dict(time_tile=24), spiir.SPIIR_E_INVAL),                  # not a multiple of 16
     (dict(time_tile=8192), spiir.SPIIR_E_INVAL),
-    (dict(queue_wgs=9), spiir.SPIIR_E_INVAL),
-    (dict(queue_wgs=-1), spiir.SPIIR_E_INVAL),
+    (dict(balance_wgs=9), spiir.SPIIR_E_INVAL),
+    (dict(balance_wgs=-1), spiir.SPIIR_E_INVAL),
     (dict(mode=7), spiir.SPIIR_E_INVAL),
     (dict(mode=1, block_len=96), spiir.SPIIR_E_INVAL),          # unsupported block length
     (dict(mode=1, max_chunk=1000), spiir.SPIIR_E_INVAL),        # not a multiple of L
@@ -79,7 +79,7 @@ GOOD = dict(offsets=[0, 2], a=[0.5 + 0.1j, 0.9j], b=[1 + 0j, 0.5j], d=[0, 3])
 def test_create_rejects_invalid_arguments(change, expect):
     args = dict(GOOD)
     opt_keys = {"max_delay", "n_detectors", "max_chunk", "filters_per_lane", "mode", "peak_window",
-                "time_tile", "block_len", "queue_wgs"}
+                "time_tile", "block_len", "balance_wgs"}
     opts = {k: v for k, v in change.items() if k in opt_keys}
     args.update({k: v for k, v in change.items() if k not in opt_keys})
     offsets = args["offsets"]

@@ -26,8 +26,9 @@ def per_template_rel(g, g_ref, offsets):
     return np.array(out)
 
 
-@pytest.mark.parametrize("stride, n", [(128, 1000), (2048, 3000), (256, 256), (4096, 4000)])
-def test_backward_matches_oracle_gradient(gpu, stride, n):
+@pytest.mark.parametrize("stride, n, balance_wgs", [(128, 1000, 0), (2048, 3000, 0), (256, 256, 0),
+                                                  (4096, 4000, 0), (128, 3000, 2)])
+def test_backward_matches_oracle_gradient(gpu, stride, n, balance_wgs):
     import torch
     rng = np.random.default_rng(stride + n)
     bank = synth.draw_filters(rng, np.array([64, 100, 7, 256]), max_delay=500)
@@ -38,7 +39,9 @@ def test_backward_matches_oracle_gradient(gpu, stride, n):
     z_ref = oracle.filter(bank, x)
     gz = (2 * z_ref + w).astype(np.complex64)         # dL/dz of L = sum |z|^2 + Re sum conj(w) z
     ga_ref, gb_ref = oracle.grad(bank, x, gz)
-    with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=n, ckpt_stride=stride) as sb:
+    with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=n, ckpt_stride=stride,
+                                 balance_wgs=balance_wgs) as sb:
+        assert (sb.info.balance_waves > 0) == (balance_wgs > 0)
         xd = torch.from_numpy(x).cuda()
         z, ckpt = sb.forward(xd)
         assert oracle.rel_err(z.cpu().numpy(), z_ref).max() <= 1e-4

@@ -16,15 +16,15 @@ TOL_FP32 = 1e-4
 
 
 def run_stream(gpu, bank, x, chunk, *, peak_window=0, filters_per_lane=0, max_delay=0,
-               want_z=True, time_tile=0, queue_wgs=0):
+               want_z=True, time_tile=0, balance_wgs=0):
     import torch
     D, N = x.shape
     zs, pk, am = [], [], []
     with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=chunk, peak_window=peak_window,
                                  filters_per_lane=filters_per_lane, max_delay=max_delay,
-                                 time_tile=time_tile, queue_wgs=queue_wgs) as sb:
+                                 time_tile=time_tile, balance_wgs=balance_wgs) as sb:
         fits = chunk + sb.info.max_delay + 16 <= 12288
-        assert (sb.info.queue_wgs > 0) == (time_tile == 0 and fits)
+        assert (sb.info.balance_waves > 0) == (time_tile <= 0 and balance_wgs > 0 and fits)
         xd = torch.from_numpy(x).cuda()
         for lo in range(0, N, chunk):
             xc = xd[:, lo:lo + chunk].contiguous()
@@ -52,34 +52,34 @@ def test_tiny_workload_whole_and_chunked(gpu):
             check_peaks(pk[c], am[c], z[..., lo:lo + chunk], z_ref[..., lo:lo + chunk], chunk)
 
 
-@pytest.mark.parametrize("time_tile", [0, -1, 256, 16])
+@pytest.mark.parametrize("time_tile, balance_wgs", [(0, 0), (0, 3), (256, 0), (16, 0)])
 @pytest.mark.parametrize("chunk", [1, 7, 100, 512, 1000])
-def test_chunk_sizes_agree_with_oracle(gpu, chunk, time_tile):
+def test_chunk_sizes_agree_with_oracle(gpu, chunk, time_tile, balance_wgs):
     rng = np.random.default_rng(100 + chunk)
     bank = synth.draw_filters(rng, np.array([70, 130, 5]))
     n = 3000 if chunk > 1 else 400
     x = rng.standard_normal((2, n)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
-    z, _, _ = run_stream(gpu, bank, x, chunk, time_tile=time_tile)
+    z, _, _ = run_stream(gpu, bank, x, chunk, time_tile=time_tile, balance_wgs=balance_wgs)
     assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
 
 
-@pytest.mark.parametrize("time_tile, queue_wgs", [(16, 0), (256, 0), (4096, 0), (-1, 0),
-                                                  (0, 1), (0, 2), (0, 8)])
-def test_schedules_on_a_larger_bank(gpu, time_tile, queue_wgs):
+@pytest.mark.parametrize("time_tile, balance_wgs", [(16, 0), (256, 0), (4096, 0), (-1, 0),
+                                                  (0, 1), (-1, 2), (0, 8)])
+def test_schedules_on_a_larger_bank(gpu, time_tile, balance_wgs):
     # many slices and tiles: the persistent queue's dependency chains, and the slice
     # queue with few and with many resident workgroups per compute unit
     rng = np.random.default_rng(150)
     bank = synth.draw_filters(rng, rng.integers(50, 900, size=96))
     x = rng.standard_normal((3, 6144)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
-    z, pk, am = run_stream(gpu, bank, x, 2048, time_tile=time_tile, queue_wgs=queue_wgs)
+    z, pk, am = run_stream(gpu, bank, x, 2048, time_tile=time_tile, balance_wgs=balance_wgs)
     assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
 
 
-@pytest.mark.parametrize("time_tile", [0, -1, 256])
+@pytest.mark.parametrize("time_tile, balance_wgs", [(0, 0), (0, 2), (256, 0)])
 @pytest.mark.parametrize("fpl", [2, 4, 8])
-def test_filters_per_lane_and_slice_boundaries(gpu, fpl, time_tile):
+def test_filters_per_lane_and_slice_boundaries(gpu, fpl, time_tile, balance_wgs):
     # template sizes around the slot/slice boundaries: 64*fpl filters per slice
     counts = np.array([1, 63, 64, 65, 64 * fpl, 64 * fpl + 1, 3 * 64 * fpl - 7, 0, 2])
     rng = np.random.default_rng(200 + fpl)
@@ -87,7 +87,7 @@ def test_filters_per_lane_and_slice_boundaries(gpu, fpl, time_tile):
     x = rng.standard_normal((1, 2500)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
     z, pk, am = run_stream(gpu, bank, x, 2500, filters_per_lane=fpl, peak_window=500,
-                           time_tile=time_tile)
+                           time_tile=time_tile, balance_wgs=balance_wgs)
     err = oracle.rel_err(z, z_ref)
     nz = np.linalg.norm(z_ref, axis=-1) > 0
     assert err[nz].max() <= TOL_FP32
@@ -103,9 +103,9 @@ def test_delay_extremes_and_history(gpu):
     bank.d[5:10] = 2047
     x = rng.standard_normal((1, 6000)).astype(np.float32)
     z_ref = oracle.filter(bank, x)
-    for chunk, md, tt in ((512, 0, 0), (300, 4000, 256), (6000, 0, 0), (6000, 0, 512), (300, 8191, 64),
-                          (300, 8191, 0), (4000, 8191, 0)):
-        z, _, _ = run_stream(gpu, bank, x, chunk, max_delay=md, time_tile=tt)
+    for chunk, md, tt, q in ((512, 0, 0, 0), (300, 4000, 256, 0), (6000, 0, 0, 0), (6000, 0, 512, 0),
+                             (300, 8191, 64, 0), (300, 8191, 0, 2), (4000, 8191, 0, 2)):
+        z, _, _ = run_stream(gpu, bank, x, chunk, max_delay=md, time_tile=tt, balance_wgs=q)
         assert oracle.rel_err(z, z_ref).max() <= TOL_FP32
 
 
