@@ -63,8 +63,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=4)
     p.add_argument("--filters-per-lane", type=int, default=0)
     p.add_argument("--time-tile", type=int, default=0)
-    p.add_argument("--balance-wgs", type=int, default=0,
-                   help="balanced schedule: resident workgroups per compute unit (0 = off)")
+    p.add_argument("--balance-wgs", type=int, default=2,
+                   help="balanced schedule: resident workgroups per compute unit (0 = one "
+                        "wave per filter group)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-check", action="store_true")
     p.add_argument("--cpu-templates", type=int, default=1024,
@@ -390,7 +391,7 @@ def main():
             "balance_waves": info.balance_waves,
         },
         "roofline": {
-            "kernel": "scan_fp32_kernel",
+            "kernel": "scan_fp32_balanced_kernel" if info.balance_waves > 0 else "scan_fp32_kernel",
             "bound": "alu",
             "achieved": achieved_tflops,
             "peak": PEAK_FP32_TFLOPS,

@@ -1,8 +1,9 @@
 """Autotuner for the schedule of a SPIIR bank.
 
 Times candidate configurations (FP32 scan: filters per lane x schedule, where
-the schedule is one wave per filter group walking the packet or the persistent
-time-tiled work queue; split-bf16 block form: block length) on the caller's
+the schedule is one wave per filter group walking the packet, the balanced static
+schedule with a given number of resident workgroups per compute unit, or the
+persistent time-tiled work queue; split-bf16 block form: block length) on the caller's
 packet length and detector count, and returns the fastest.  Candidates run on
 the real bank, or, for the block form whose operand set grows with the number
 of templates, on a seeded sample of templates (the time per filter-sample
@@ -18,7 +19,9 @@ import numpy as np
 
 from . import spiir
 
-DEFAULT_SCAN = [dict(filters_per_lane=f, time_tile=t) for f in (2, 4, 8) for t in (0, 256, 512)]
+DEFAULT_SCAN = ([dict(filters_per_lane=f, time_tile=t) for f in (2, 4, 8) for t in (0, 512)] +
+                [dict(filters_per_lane=f, time_tile=0, balance_wgs=c)
+                 for f, c in ((2, 4), (4, 2), (4, 3), (8, 2))])
 DEFAULT_BLOCK = [dict(block_len=L) for L in (64, 128, 256)]
 
 

@@ -10,8 +10,8 @@ import synth
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("time_tile", [0, 256])
-def test_graph_replay_matches_eager_and_oracle(gpu, time_tile):
+@pytest.mark.parametrize("time_tile, balance_wgs", [(0, 0), (256, 0), (0, 2)])
+def test_graph_replay_matches_eager_and_oracle(gpu, time_tile, balance_wgs):
     import torch
     w = synth.batching()
     bank, D, chunk = w.bank, w.n_det, w.chunk
@@ -20,7 +20,7 @@ def test_graph_replay_matches_eager_and_oracle(gpu, time_tile):
     x = torch.from_numpy(x_host).cuda()
     packets = [x[:, i * chunk:(i + 1) * chunk].contiguous() for i in range(n_packets)]
     T = bank.n_templates
-    kw = dict(n_detectors=D, max_chunk=chunk, time_tile=time_tile)
+    kw = dict(n_detectors=D, max_chunk=chunk, time_tile=time_tile, balance_wgs=balance_wgs)
     with gpu.SpiirBank.from_bank(bank, **kw) as g_bank, gpu.SpiirBank.from_bank(bank, **kw) as e_bank:
         zg = torch.empty((D, T, chunk), dtype=torch.complex64, device="cuda")
         pg = torch.empty((D, T, 1), dtype=torch.float32, device="cuda")
@@ -43,7 +43,7 @@ def test_graph_replay_matches_eager_and_oracle(gpu, time_tile):
     z = np.concatenate(zs, axis=-1)
     z_ref = oracle.filter(bank.subset(pick), x_host)
     err = oracle.rel_err(z, z_ref)
-    print(f"batching (time_tile {time_tile}): max rel err {err.max():.3e}")
+    print(f"batching (time_tile {time_tile}, balance {balance_wgs}): max rel err {err.max():.3e}")
     assert err.max() <= 1e-4
 
 
@@ -56,7 +56,9 @@ def test_autotuner_picks_a_measured_candidate(gpu):
     packets = [x[:, i * 512:(i + 1) * 512].contiguous() for i in range(4)]
     best, trials = tune.autotune(bank, packets, reps=3, block_sample_templates=64,
                                  scan_candidates=[dict(filters_per_lane=4, time_tile=0),
-                                                  dict(filters_per_lane=8, time_tile=256)],
+                                                  dict(filters_per_lane=8, time_tile=256),
+                                                  dict(filters_per_lane=4, time_tile=0,
+                                                       balance_wgs=2)],
                                  block_candidates=[dict(block_len=128)])
-    assert len(trials) == 3 and best in trials
+    assert len(trials) == 4 and best in trials
     assert best.updates_per_s == max(t.updates_per_s for t in trials)
