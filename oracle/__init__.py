@@ -64,6 +64,7 @@ def _load():
         for f in (lib.spo_filter, lib.spo_peaks, lib.spo_grad, lib.spo_overlap_grad):
             f.restype = ctypes.c_int
         lib.spo_noise_power.argtypes = [_I32, _P, _P, _P, _P, _P]
+        lib.spo_autocorr.argtypes = [_I32, _P, _P, _P, _P, _I32, _P]
         lib.spo_noise_power.restype = ctypes.c_int
         lib.spo_threads.argtypes = []
         lib.spo_threads.restype = ctypes.c_int
@@ -253,6 +254,47 @@ def triggers(z: np.ndarray, weight: np.ndarray, threshold: float, window: int):
     got = idx >= 0
     snr[got] = np.sqrt(snr[got]).astype(np.float32)
     return snr, idx
+
+
+def autocorr(bank, nj: int) -> np.ndarray:
+    """R_t[j] = sum_m u_t[m+j] conj(u_t[m]), j = 0..nj, of each template's impulse
+    response u_t (closed form, FP64): the correlation of a template with itself used
+    by the signal-consistency statistic of Section II.C.1.  complex128 [T][nj+1]."""
+    offsets, a, b, d = _bank_arrays(bank)
+    out = np.empty((bank.n_templates, nj + 1), dtype=np.complex128)
+    rc = _load().spo_autocorr(bank.n_templates, _ptr(offsets), _ptr(a), _ptr(b), _ptr(d), int(nj),
+                              _ptr(out))
+    _check(rc, "autocorr")
+    return out
+
+
+def xi2(z: np.ndarray, index: np.ndarray, R: np.ndarray, nj: int) -> np.ndarray:
+    """The signal-consistency statistic of Section II.C.1 at candidate samples.
+
+    For row (detector, template) and candidate sample c = index[d, t, w] (-1 = none):
+      xi2 = sum_{j=-nj..nj} |v[c+j] - v[c] A[j]|^2 / sum_{j=-nj..nj} (2 - 2|A[j]|^2)
+    with A[j] = R_t[j] / R_t[0] (A[-j] = conj(A[j])) and v = z * sqrt(2 / R_t[0]), the SNR
+    normalised to unit variance per quadrature for unit white input (so that a
+    noise-only series gives a reduced chi-square of mean 1).  NaN where there is no
+    candidate or c +- nj leaves the series.  z: complex [D][T][n]; R: [T][>= nj+1].
+    Plain FP64 loops.
+    """
+    z = np.asarray(z, dtype=np.complex128)
+    D, T, n = z.shape
+    out = np.full(index.shape, np.nan, dtype=np.float64)
+    for t in range(T):
+        r0 = R[t, 0].real
+        A = np.concatenate([np.conj(R[t, nj:0:-1]), R[t, :nj + 1]]) / r0     # j = -nj..nj
+        den = np.sum(2.0 - 2.0 * np.abs(A) ** 2)
+        scale = np.sqrt(2.0 / r0)
+        for det in range(D):
+            for w in range(index.shape[2]):
+                c = int(index[det, t, w])
+                if c < 0 or c - nj < 0 or c + nj >= n:
+                    continue
+                v = z[det, t, c - nj:c + nj + 1] * scale
+                out[det, t, w] = np.sum(np.abs(v - v[nj] * A) ** 2) / den
+    return out
 
 
 def threads() -> int:

@@ -408,3 +408,75 @@ int spo_noise_power(int32_t n_templates, const int32_t *offsets, const double *a
     }
     return SPO_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Signal-consistency statistic (Section II.C.1): the correlation function   */
+/* of a template with itself.                                                */
+/* ------------------------------------------------------------------------ */
+
+/* (re, im) of p^e for integer e >= 0, by repeated squaring. */
+static void cpow_int(double pr, double pi, int64_t e, double *rr, double *ri)
+{
+    double ar = 1.0, ai = 0.0, sr = pr, si = pi;
+    for (; e > 0; e >>= 1) {
+        if (e & 1) {
+            const double tr = ar * sr - ai * si;
+            ai = ar * si + ai * sr;
+            ar = tr;
+        }
+        const double qr = sr * sr - si * si;
+        si = 2.0 * sr * si;
+        sr = qr;
+    }
+    *rr = ar;
+    *ri = ai;
+}
+
+/*
+ * R_t[j] = sum_m u_t[m+j] conj(u_t[m]) for j = 0..nj, where u_t is the template's
+ * response to a unit impulse, u_t[m] = sum_k b_k a_k^(m-d_k) [m >= d_k].  The sum
+ * over m is geometric for every pair of filters (k, l):
+ *   sum over m >= max(d_l, d_k - j) of a_k^(m+j-d_k) conj(a_l)^(m-d_l)
+ *     = a_k^(d_l+j-d_k) / (1 - a_k conj(a_l))          if d_l + j >= d_k,
+ *     = conj(a_l)^(d_k-j-d_l) / (1 - a_k conj(a_l))    otherwise,
+ * times b_k conj(b_l).  R_t[-j] = conj(R_t[j]); R_t[0] = E|z_t|^2 for unit white input.
+ * R: [T][nj+1] complex.
+ */
+int spo_autocorr(int32_t n_templates, const int32_t *offsets, const double *a, const double *b,
+                 const int32_t *d, int32_t nj, double *R)
+{
+    if (n_templates < 0 || nj < 0)
+        return SPO_EINVAL;
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int32_t t = 0; t < n_templates; ++t) {
+        for (int32_t j = 0; j <= nj; ++j) {
+            double accr = 0.0, acci = 0.0;
+            for (int64_t k = offsets[t]; k < offsets[t + 1]; ++k) {
+                const double akr = a[2 * k], aki = a[2 * k + 1];
+                for (int64_t l = offsets[t]; l < offsets[t + 1]; ++l) {
+                    const double alr = a[2 * l], ali = -a[2 * l + 1];      /* conj(a_l) */
+                    double pr, pi;
+                    const int64_t e = (int64_t)d[l] + j - d[k];
+                    if (e >= 0)
+                        cpow_int(akr, aki, e, &pr, &pi);
+                    else
+                        cpow_int(alr, ali, -e, &pr, &pi);
+                    /* num = b_k conj(b_l) * power */
+                    const double gr = b[2 * k] * b[2 * l] + b[2 * k + 1] * b[2 * l + 1];
+                    const double gi = b[2 * k + 1] * b[2 * l] - b[2 * k] * b[2 * l + 1];
+                    const double nr = gr * pr - gi * pi;
+                    const double ni = gr * pi + gi * pr;
+                    /* den = 1 - a_k conj(a_l) */
+                    const double dr = 1.0 - (akr * alr - aki * ali);
+                    const double di = -(akr * ali + aki * alr);
+                    const double den2 = dr * dr + di * di;
+                    accr += (nr * dr + ni * di) / den2;
+                    acci += (ni * dr - nr * di) / den2;
+                }
+            }
+            R[2 * ((int64_t)t * (nj + 1) + j)] = accr;
+            R[2 * ((int64_t)t * (nj + 1) + j) + 1] = acci;
+        }
+    }
+    return SPO_OK;
+}

@@ -3,8 +3,10 @@
 Sources of truth used here: the closed-form summed impulse response of the
 SPIIR bank (Section II.B.1), a brute-force direct convolution, scipy's
 ``lfilter``, the steady-state frequency response, the white-noise output
-variance, linearity / shift / chunking invariance, the block-carry identity, and
-the paper's cost-model arithmetic (Section II.B.2).
+variance, linearity / shift / chunking invariance, the block-carry identity, the
+paper's cost-model arithmetic (Section II.B.2), and for the signal-consistency
+statistic (Section II.C.1) the brute-force correlation of the impulse response, the
+noise power at lag 0, exact special cases and its unit mean on white noise.
 """
 import json
 import math
@@ -449,3 +451,64 @@ def test_triggers_brute_force_with_ties_and_threshold():
     assert idx[1, 1, 1] == 70
     # every trigger is above threshold and at most one per (template, window)
     assert np.all(snr[idx >= 0] > 4.0) and np.all(snr[idx < 0] == 0)
+
+
+# ---- signal-consistency statistic (Section II.C.1) ----
+
+def test_autocorr_matches_brute_force_correlation():
+    # R_t[j] = sum_m u_t[m+j] conj(u_t[m]) from the impulse response itself, both signs of j
+    bank = small_bank(51, [9, 4, 13], max_delay=300, tau=(0.002, 0.03))
+    nj, n = 120, 7000            # |a|^n < 1e-40 for tau <= 0.03 s
+    u = oracle.filter(bank, synth.impulse(n))[0]
+    R = oracle.autocorr(bank, nj)
+    for t in range(bank.n_templates):
+        for j in range(-nj, nj + 1):
+            if j >= 0:
+                bf = np.sum(u[t, j:] * np.conj(u[t, :n - j]))
+                ref = R[t, j]
+            else:
+                bf = np.sum(u[t, :n + j] * np.conj(u[t, -j:]))
+                ref = np.conj(R[t, -j])
+            assert abs(bf - ref) <= 1e-10 * abs(R[t, 0])
+
+
+def test_autocorr_lag0_is_noise_power():
+    bank = small_bank(52, [5, 11], max_delay=2047, tau=(0.005, 4.0))
+    R = oracle.autocorr(bank, 3)
+    assert np.allclose(R[:, 0].real, oracle.noise_power(bank), rtol=1e-12)
+    assert np.all(np.abs(R[:, 0].imag) <= 1e-12 * R[:, 0].real)
+
+
+def test_xi2_special_cases():
+    # a series that is exactly the scaled autocorrelation around the candidate gives 0;
+    # one extra complex offset e at one lag gives |e|^2 * (2 / R0) / sum(2 - 2|A|^2)
+    bank = small_bank(53, [6, 8], max_delay=100, tau=(0.002, 0.02))
+    nj, n, c = 50, 400, 200
+    R = oracle.autocorr(bank, nj)
+    z = np.zeros((1, 2, n), dtype=np.complex128)
+    for t in range(2):
+        A = np.concatenate([np.conj(R[t, nj:0:-1]), R[t, :nj + 1]]) / R[t, 0].real
+        z[0, t, c - nj:c + nj + 1] = (3.0 - 1.5j) * A
+    e = 0.7 + 0.2j
+    z[0, 1, c + 7] += e
+    idx = np.array([[[c, -1], [c, 5]]], dtype=np.int32)     # second column: none / too close
+    x2 = oracle.xi2(z, idx, R, nj)
+    A1 = np.concatenate([np.conj(R[1, nj:0:-1]), R[1, :nj + 1]]) / R[1, 0].real
+    expect = abs(e) ** 2 * (2.0 / R[1, 0].real) / np.sum(2 - 2 * np.abs(A1) ** 2)
+    assert abs(x2[0, 0, 0]) < 1e-24
+    assert abs(x2[0, 1, 0] - expect) < 1e-12 * expect
+    assert np.isnan(x2[0, 0, 1]) and np.isnan(x2[0, 1, 1])
+
+
+def test_xi2_has_mean_one_on_white_noise():
+    # reduced chi-square: for unit white input every term has expectation 2 - 2|A[j]|^2
+    bank = small_bank(54, [8, 8, 8], max_delay=150, tau=(0.002, 0.01))
+    nj, n = 60, 240_000
+    x = np.random.default_rng(55).standard_normal(n)
+    z = oracle.filter(bank, x)
+    R = oracle.autocorr(bank, nj)
+    pos = np.arange(2000, n - nj - 1, 2 * nj + 1)
+    idx = np.broadcast_to(pos, (1, bank.n_templates, len(pos))).astype(np.int32).copy()
+    x2 = oracle.xi2(z, idx, R, nj)
+    m = float(np.mean(x2))
+    assert abs(m - 1.0) < 0.02, m     # mean 1.001, std of the mean 0.003 at this seed
