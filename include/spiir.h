@@ -188,6 +188,37 @@ spiir_status spiir_triggers(const float *z, int32_t n_det, int32_t n_templates, 
                             float *snr, int32_t *index, void *stream);
 
 /*
+ * ---- Signal-consistency statistic (Section II.C.1) ----
+ * The correlation of each template with itself,
+ *   R_t[j] = sum_m u_t[m+j] conj(u_t[m]),  j = 0..nj   (R_t[-j] = conj(R_t[j])),
+ * of the template's impulse response u_t[m] = sum_k b_k a_k^(m-d_k) [m >= d_k]; in
+ * closed form (a geometric sum per pair of filters), in FP64 on the GPU from the
+ * bank's coefficients (float32 values promoted exactly).  R_t[0] = E|z_t|^2 for unit
+ * white input.
+ *   nj  1..4096
+ *   R   device double [T][nj+1][2] (complex128, interleaved)
+ * Synchronous: allocates, fills and frees temporary device copies of the coefficients.
+ */
+spiir_status spiir_bank_autocorr(const spiir_bank *bank, int32_t nj, double *R, void *stream);
+
+/*
+ * xi^2 at candidate samples (Section II.C.1): for row (detector, template) and its
+ * candidate sample c,
+ *   xi^2 = sum_{j=-nj..nj} |v[c+j] - v[c] A[j]|^2 / sum_{j=-nj..nj} (2 - 2|A[j]|^2),
+ * A[j] = R_t[j] / R_t[0], v = z * sqrt(2 / R_t[0]) (unit variance per quadrature for unit
+ * white input, so that noise alone gives a reduced chi-square of mean 1).  Sums in FP64.
+ *   z      device complex64 [n_det][n_templates][n]
+ *   index  device int32 [n_det][n_templates][n_win]: candidate sample in [0, n), -1 = none
+ *          (the `index` output of spiir_triggers)
+ *   R      device double [n_templates][nj+1][2] from spiir_bank_autocorr with the same nj
+ *   xi2    device float32 [n_det][n_templates][n_win]; NaN where there is no candidate or
+ *          c - nj < 0 or c + nj >= n (the caller keeps enough of the series around it)
+ */
+spiir_status spiir_xi2(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                       const int32_t *index, int32_t n_win, const double *R, int32_t nj, float *xi2,
+                       void *stream);
+
+/*
  * ---- Differentiation (FP32 scan mode only) ----
  * For fitting coefficients to a target response (the overlap of Eq. overlap,
  * Section II.B.1, between a template and the summed filter response).  These

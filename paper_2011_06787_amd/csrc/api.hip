@@ -668,6 +668,62 @@ spiir_status spiir_triggers(const float *z, int32_t n_det, int32_t n_templates, 
     return SPIIR_OK;
 }
 
+spiir_status spiir_bank_autocorr(const spiir_bank *h, int32_t nj, double *R, void *stream) {
+    if (h == nullptr || R == nullptr) return fail(SPIIR_E_INVAL, "bank or R is NULL");
+    if (nj < 1 || nj > 4096) return fail(SPIIR_E_INVAL, "nj must be in [1, 4096]");
+    const spiir::Bank &bk = h->bk;
+    const int32_t T = bk.n_templates;
+    const int64_t F = bk.n_filters;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // temporary device copies of the coefficients in template order
+    int32_t *d_off = nullptr, *d_d = nullptr;
+    float2 *d_a = nullptr, *d_b = nullptr;
+    auto release = [&]() {
+        (void)hipFree(d_off);
+        (void)hipFree(d_d);
+        (void)hipFree(d_a);
+        (void)hipFree(d_b);
+    };
+    const size_t fb = (size_t)std::max<int64_t>(F, 1);
+    if (hipMalloc((void **)&d_off, sizeof(int32_t) * (T + 1)) != hipSuccess ||
+        hipMalloc((void **)&d_d, sizeof(int32_t) * fb) != hipSuccess ||
+        hipMalloc((void **)&d_a, sizeof(float2) * fb) != hipSuccess ||
+        hipMalloc((void **)&d_b, sizeof(float2) * fb) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return fail(SPIIR_E_NOMEM, "autocorr: temporary device allocation failed");
+    }
+    hipError_t e = hipMemcpyAsync(d_off, bk.h_offsets.data(), sizeof(int32_t) * (T + 1),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && F > 0)
+        e = hipMemcpyAsync(d_d, bk.h_delay.data(), sizeof(int32_t) * F, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && F > 0)
+        e = hipMemcpyAsync(d_a, bk.h_a.data(), sizeof(float2) * F, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && F > 0)
+        e = hipMemcpyAsync(d_b, bk.h_b.data(), sizeof(float2) * F, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = spiir::launch_autocorr(T, d_off, d_a, d_b, d_d, nj, reinterpret_cast<double2 *>(R), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    release();
+    if (e != hipSuccess) return fail(SPIIR_E_HIP, std::string("autocorr: ") + hipGetErrorString(e));
+    return SPIIR_OK;
+}
+
+spiir_status spiir_xi2(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                       const int32_t *index, int32_t n_win, const double *R, int32_t nj, float *xi2,
+                       void *stream) {
+    if (n_det < 0 || n_templates < 0 || n < 0 || n_win < 0)
+        return fail(SPIIR_E_INVAL, "sizes must be >= 0");
+    if (nj < 1 || nj > 4096) return fail(SPIIR_E_INVAL, "nj must be in [1, 4096]");
+    if ((int64_t)n_det * n_templates * n_win == 0) return SPIIR_OK;
+    if (z == nullptr || index == nullptr || R == nullptr || xi2 == nullptr)
+        return fail(SPIIR_E_INVAL, "z, index, R and xi2 must be non-NULL");
+    SPIIR_HIP(spiir::launch_xi2(reinterpret_cast<const float2 *>(z), n_det, n_templates, n, index,
+                                n_win, reinterpret_cast<const double2 *>(R), nj, xi2,
+                                static_cast<hipStream_t>(stream)));
+    return SPIIR_OK;
+}
+
 spiir_status spiir_ckpt_count(const spiir_bank *h, int32_t n, int64_t *n_values) {
     if (h == nullptr || n_values == nullptr) return fail(SPIIR_E_INVAL, "bank or n_values is NULL");
     const spiir::Bank &bk = h->bk;

@@ -168,6 +168,11 @@ hipError_t launch_triggers(const float2 *z, int32_t n_det, int32_t n_templates, 
                            const float *weight, float threshold, int32_t window,
                            unsigned long long *work, float *snr, int32_t *index, hipStream_t s);
 hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *z, hipStream_t s);
+hipError_t launch_autocorr(int32_t n_templates, const int32_t *offsets, const float2 *a,
+                           const float2 *b, const int32_t *d, int32_t nj, double2 *R, hipStream_t s);
+hipError_t launch_xi2(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
+                      const int32_t *index, int32_t n_win, const double2 *R, int32_t nj, float *xi2,
+                      hipStream_t s);
 int32_t block_state_xwin(const Bank &bk);
 size_t block_state_lds_bytes(const Bank &bk);
 hipError_t prepare_block_bf16(const Bank &bk);

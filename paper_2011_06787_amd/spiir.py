@@ -31,6 +31,7 @@ EXPORTS = (
     "spiir_bank_get_info", "spiir_filter_chunk", "spiir_peaks", "spiir_last_error",
     "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count", "spiir_forward",
     "spiir_backward", "spiir_bank_set_coeffs", "spiir_bank_noise_power", "spiir_triggers",
+    "spiir_bank_autocorr", "spiir_xi2",
 )
 
 
@@ -101,6 +102,9 @@ def load():
     lib.spiir_bank_noise_power.argtypes = [_P, _P]
     lib.spiir_triggers.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                    ctypes.c_float, ctypes.c_int32, _P, _P, _P, _P]
+    lib.spiir_bank_autocorr.argtypes = [_P, ctypes.c_int32, _P, _P]
+    lib.spiir_xi2.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                              _P, ctypes.c_int32, _P, _P]
     lib.spiir_last_error.argtypes = []
     lib.spiir_last_error.restype = ctypes.c_char_p
     for name in ("spiir_bank_create", "spiir_bank_destroy", "spiir_bank_reset",
@@ -270,6 +274,15 @@ class SpiirBank:
         _check("spiir_bank_noise_power", load().spiir_bank_noise_power(self._h, out.ctypes.data))
         return out
 
+    def autocorr(self, nj: int = 175, stream=None):
+        """R_t[j], j = 0..nj, of each template's impulse response (Sec. II.C.1): cuda
+        complex128 [T][nj+1], computed in closed form on the GPU (synchronous)."""
+        import torch
+        R = torch.empty((self.n_templates, nj + 1), dtype=torch.complex128, device="cuda")
+        _check("spiir_bank_autocorr",
+               load().spiir_bank_autocorr(self._h, int(nj), R.data_ptr(), _stream_ptr(stream)))
+        return R
+
     def set_timing(self, enable: bool, capacity: int = 4096):
         """Bracket the main filtering kernel with HIP events (see spiir.h)."""
         _check("spiir_bank_set_timing",
@@ -376,3 +389,23 @@ def triggers(z, weight, threshold: float = 4.0, window: int = 2048, work=None, s
                                                    float(threshold), int(window), work.data_ptr(),
                                                    snr.data_ptr(), idx.data_ptr(), _stream_ptr(stream)))
     return snr, idx
+
+
+def xi2(z, index, R, nj: int, stream=None):
+    """Signal-consistency statistic (Sec. II.C.1) at candidate samples.
+
+    ``z`` cuda complex64 [D][T][n]; ``index`` cuda int32 [D][T][W] (candidate samples,
+    -1 = none, e.g. from ``triggers``); ``R`` cuda complex128 [T][nj+1] from
+    ``SpiirBank.autocorr(nj)``.  Returns cuda float32 [D][T][W], NaN where undefined.
+    """
+    import torch
+    assert z.is_cuda and z.dtype == torch.complex64 and z.is_contiguous() and z.dim() == 3
+    assert index.dtype == torch.int32 and index.is_contiguous() and index.dim() == 3
+    assert R.dtype == torch.complex128 and R.is_contiguous() and R.shape[-1] == nj + 1
+    D, T, n = (int(v) for v in z.shape)
+    assert index.shape[0] == D and index.shape[1] == T and R.shape[0] == T
+    W = int(index.shape[2])
+    out = torch.empty((D, T, W), dtype=torch.float32, device=z.device)
+    _check("spiir_xi2", load().spiir_xi2(z.data_ptr(), D, T, n, index.data_ptr(), W, R.data_ptr(),
+                                         int(nj), out.data_ptr(), _stream_ptr(stream)))
+    return out

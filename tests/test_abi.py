@@ -100,6 +100,10 @@ def test_null_and_shape_errors_without_gpu():
     assert lib.spiir_bank_destroy(None) == spiir.SPIIR_OK
     assert lib.spiir_peaks(None, 4, 16, 0, None, None, None) == spiir.SPIIR_E_INVAL   # window 0
     assert lib.spiir_peaks(None, 4, 16, 8, None, None, None) == spiir.SPIIR_E_INVAL   # NULL buffers
+    assert lib.spiir_bank_autocorr(None, 10, None, None) == spiir.SPIIR_E_INVAL
+    assert lib.spiir_xi2(None, 1, 2, 100, None, 1, None, 0, None, None) == spiir.SPIIR_E_INVAL  # nj 0
+    assert lib.spiir_xi2(None, 1, 2, 100, None, 1, None, 5, None, None) == spiir.SPIIR_E_INVAL  # NULLs
+    assert lib.spiir_xi2(None, 0, 2, 100, None, 1, None, 5, None, None) == spiir.SPIIR_OK      # empty
     assert lib.spiir_peaks(None, 0, 16, 8, None, None, None) == spiir.SPIIR_OK        # empty no-op
     assert lib.spiir_peaks(None, -1, 16, 8, None, None, None) == spiir.SPIIR_E_INVAL
 
