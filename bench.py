@@ -82,6 +82,8 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="batching: skip the autotuner")
     p.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
     p.add_argument("--diff-only", action="store_true")
+    p.add_argument("--no-xi2", action="store_true", help="skip the signal-consistency section")
+    p.add_argument("--xi2-only", action="store_true")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB four times "
                         "(calibrates the HBM byte counters) and exit")
@@ -299,6 +301,52 @@ def differentiation_run(args, dev):
     return out
 
 
+def xi2_run(args, dev):
+    """Signal-consistency statistic (Sec. II.C.1) on the realistic bank: the template
+    autocorrelation (nj = 175 lags, FP64 closed form on the GPU), then for one 1-s packet
+    the triggers (threshold 4 on the normalised SNR, one per template per 512 samples)
+    and xi^2 at each of them; R checked against the FP64 oracle on seeded templates."""
+    import torch
+    import oracle
+    from paper_2011_06787_amd import spiir
+    w = synth.realistic()
+    bank, chunk, nj = w.bank, w.chunk, 175
+    x = torch.from_numpy(w.input()[:, :4 * chunk]).to(dev)
+    T = bank.n_templates
+    out = {"workload": "realistic bank (1024 templates, 521,135 filters), nj = 175, one 1-s packet",
+           "nj": nj}
+    with spiir.SpiirBank.from_bank(bank, max_chunk=chunk) as sb:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R = sb.autocorr(nj)
+        out["autocorr_ms"] = (time.perf_counter() - t0) * 1e3
+        weight = (2.0 / R[:, 0].real).to(torch.float32).contiguous()
+        for i in range(3):                                   # warm the stream state
+            z, _, _ = sb.filter_chunk(x[:, i * chunk:(i + 1) * chunk].contiguous())
+        z, _, _ = sb.filter_chunk(x[:, 3 * chunk:4 * chunk].contiguous())
+        snr, idx = spiir.triggers(z, weight, 4.0, 512)
+        xi = spiir.xi2(z, idx, R, nj)                        # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            xi = spiir.xi2(z, idx, R, nj)
+        e1.record()
+        torch.cuda.synchronize()
+        ok = ~torch.isnan(xi)
+        out["candidates"] = int((idx >= 0).sum())
+        out["xi2_evaluated"] = int(ok.sum())
+        out["xi2_us"] = e0.elapsed_time(e1) * 1e3 / 10
+        out["xi2_mean"] = float(xi[ok].mean()) if int(ok.sum()) else None
+        pick = sorted(set([0, T - 1]) | set(np.random.default_rng(7).choice(T, 2, replace=False).tolist()))
+        R_ref = oracle.autocorr(bank.subset(pick), nj)
+        Rg = R.cpu().numpy()[pick]
+        out["autocorr_rel_err_max"] = float(np.max(np.abs(Rg - R_ref) / np.abs(R_ref[:, :1])))
+    log(f"xi2: autocorr {out['autocorr_ms']:.1f} ms, {out['xi2_evaluated']} candidates in "
+        f"{out['xi2_us']:.1f} us, mean xi2 {out['xi2_mean']}")
+    return out
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -321,6 +369,9 @@ def main():
         return
     if args.diff_only:
         print(json.dumps({"differentiation": differentiation_run(args, dev)}), flush=True)
+        return
+    if args.xi2_only:
+        print(json.dumps({"xi2": xi2_run(args, dev)}), flush=True)
         return
     w = synth.realistic()
     bank = w.bank
@@ -447,6 +498,8 @@ def main():
         result["batching"] = batching_run(args, dev)
     if not args.no_diff:
         result["differentiation"] = differentiation_run(args, dev)
+    if not args.no_xi2:
+        result["xi2"] = xi2_run(args, dev)
     print(json.dumps(result), flush=True)
 
 
