@@ -297,6 +297,62 @@ def xi2(z: np.ndarray, index: np.ndarray, R: np.ndarray, nj: int) -> np.ndarray:
     return out
 
 
+def coherent_map(z: np.ndarray, index: np.ndarray, U: np.ndarray, tau: np.ndarray,
+                 shifts: np.ndarray):
+    """Coherent and null SNR^2 of every candidate at every sky direction and time shift
+    (Section II.C.1, Eq. llr_form, and the null statistic of the appendix), FP64 loops.
+
+    The z_I of Eq. llr_form form a vector (the per-detector inner products of the
+    appendix); a diagonal matrix there would drop the phase coherence.  For the
+    candidate of detector I, template t, window w at sample c = index[I, t, w], shift k
+    and direction p, detector J contributes v_J = z[J, t, s_J] with
+        s_J = c + tau[p, J] - tau[p, I] + shifts[k, J] - shifts[k, I],
+    and with U = U[p]:
+        rho_C^2 = sum_{i < 2} |sum_J U[J, i] v_J|^2      (projection on the signal plane)
+        rho_N^2 = sum_{i >= 2} |sum_J U[J, i] v_J|^2     (projection on the null space).
+    Returns (rho_C^2, rho_N^2) as float64 [D][T][W][K][P], NaN where there is no
+    candidate or some s_J (any p) falls outside [0, n).
+    """
+    z = np.asarray(z, dtype=np.complex128)
+    U = np.asarray(U, dtype=np.float64)
+    D, T, n = z.shape
+    W, K, P = index.shape[2], shifts.shape[0], U.shape[0]
+    rc = np.full((D, T, W, K, P), np.nan)
+    rn = np.full((D, T, W, K, P), np.nan)
+    for I in range(D):
+        for t in range(T):
+            for w in range(W):
+                c = int(index[I, t, w])
+                if c < 0:
+                    continue
+                for k in range(K):
+                    s = c + (tau - tau[:, I:I + 1]) + (shifts[k] - shifts[k, I])[None, :]  # [P][D]
+                    if s.min() < 0 or s.max() >= n:
+                        continue
+                    for p in range(P):
+                        v = np.array([z[J, t, s[p, J]] for J in range(D)])
+                        proj = U[p].T @ v
+                        rc[I, t, w, k, p] = np.sum(np.abs(proj[:2]) ** 2)
+                        rn[I, t, w, k, p] = np.sum(np.abs(proj[2:]) ** 2)
+    return rc, rn
+
+
+def coherent(z, index, U, tau, shifts):
+    """Per candidate and time shift: the largest rho_C^2 over the sky directions, its
+    direction (lowest on ties) and rho_N^2 there.  float64 / int32 [D][T][W][K];
+    NaN / -1 where coherent_map is undefined."""
+    rc, rn = coherent_map(z, index, U, tau, shifts)
+    ok = ~np.isnan(rc[..., 0])
+    pix = np.full(ok.shape, -1, dtype=np.int32)
+    best = np.full(ok.shape, np.nan)
+    null = np.full(ok.shape, np.nan)
+    arg = np.argmax(np.where(np.isnan(rc), -np.inf, rc), axis=-1)
+    pix[ok] = arg[ok]
+    best[ok] = np.take_along_axis(rc, arg[..., None], axis=-1)[..., 0][ok]
+    null[ok] = np.take_along_axis(rn, arg[..., None], axis=-1)[..., 0][ok]
+    return best, pix, null
+
+
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().spo_threads())

@@ -244,3 +244,43 @@ WORKLOADS = {
     "batching": batching,
     "differentiation": differentiation,
 }
+
+
+# ---- coherent search inputs (Section II.C.1) ----
+
+@dataclasses.dataclass
+class SkyTables:
+    """Per sky direction p: an orthogonal N_d x N_d matrix U[p] (stands in for the SVD
+    factor of the noise-weighted detector response) and the arrival-time offset of every
+    detector in samples, tau[p][J].  Detector geometry and sensitivities are not in
+    the paper, so the tables are random: U from the QR factorisation of a Gaussian
+    matrix (sign-fixed), tau uniform in [-max_offset, max_offset] (44 samples ~ the
+    21 ms light travel time across the Earth at 2048 Hz)."""
+    U: np.ndarray      # float32 [P][N_d][N_d]
+    tau: np.ndarray    # int32 [P][N_d]
+
+    @property
+    def n_pix(self) -> int:
+        return int(self.U.shape[0])
+
+
+def sky_tables(seed: int, n_det: int, n_pix: int, max_offset: int = 44) -> SkyTables:
+    """Draw order from ``default_rng(seed)``: n_pix Gaussian N_d x N_d matrices, then the
+    offsets [n_pix][N_d]."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n_pix, n_det, n_det))
+    U = np.empty_like(g)
+    for p in range(n_pix):
+        q, r = np.linalg.qr(g[p])
+        U[p] = q * np.sign(np.diag(r))[None, :]
+    tau = rng.integers(-max_offset, max_offset + 1, size=(n_pix, n_det))
+    return SkyTables(U.astype(np.float32), tau.astype(np.int32))
+
+
+def time_shifts(n_det: int, n_shifts: int, step: int = 205) -> np.ndarray:
+    """Background time shifts: shift k (k = 0..n_shifts-1) moves detector J's series by
+    k * step * J samples (detector 0 stays; step 205 samples ~ 0.1 s at 2048 Hz), so shift
+    0 is the unshifted foreground.  int32 [n_shifts][N_d]."""
+    k = np.arange(n_shifts)[:, None]
+    j = np.arange(n_det)[None, :]
+    return (k * step * j).astype(np.int32)

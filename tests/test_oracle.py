@@ -512,3 +512,80 @@ def test_xi2_has_mean_one_on_white_noise():
     x2 = oracle.xi2(z, idx, R, nj)
     m = float(np.mean(x2))
     assert abs(m - 1.0) < 0.02, m     # mean 1.001, std of the mean 0.003 at this seed
+
+
+# ---- coherent search (Section II.C.1) ----
+
+def _rand_z(rng, D, T, n, scale=1.0):
+    return (rng.standard_normal((D, T, n)) + 1j * rng.standard_normal((D, T, n))) * scale
+
+
+def test_coherent_plus_null_is_total_power():
+    # Eq. null_def: rho_N^2 = sum_I |z_I|^2 - rho_C^2 (U orthogonal); here rho_N^2 comes from
+    # the null-space columns, so this checks the two projections against each other
+    rng = np.random.default_rng(71)
+    D, T, n = 3, 2, 400
+    z = _rand_z(rng, D, T, n)
+    tab = synth.sky_tables(72, D, 40)
+    sh = synth.time_shifts(D, 2, step=20)
+    idx = np.array([[[150, 220]] * T] * D, dtype=np.int32)
+    rc, rn = oracle.coherent_map(z, idx, tab.U, tab.tau, sh)
+    for I in range(D):
+        for t in range(T):
+            for w in range(2):
+                c = idx[I, t, w]
+                for k in range(2):
+                    for p in range(40):
+                        s = c + tab.tau[p] - tab.tau[p, I] + sh[k] - sh[k, I]
+                        tot = sum(abs(z[J, t, s[J]]) ** 2 for J in range(D))
+                        assert abs(rc[I, t, w, k, p] + rn[I, t, w, k, p] - tot) <= 1e-6 * tot
+
+
+def test_coherent_signal_in_the_plane_is_found():
+    # v = U[p][:, :2] s at direction p: rho_C^2 = |s|^2 there, no null power, and every
+    # other direction projects less
+    rng = np.random.default_rng(73)
+    D, n, c, p0 = 3, 300, 150, 17
+    tab = synth.sky_tables(74, D, 64)
+    U = tab.U.astype(np.float64)
+    s = np.array([2.0 - 1.0j, 0.5 + 3.0j])
+    v = U[p0][:, :2] @ s
+    z = np.zeros((D, 1, n), dtype=np.complex128)
+    idx = np.full((D, 1, 1), -1, dtype=np.int32)
+    idx[0, 0, 0] = c
+    for J in range(D):
+        z[J, 0, c + tab.tau[p0, J] - tab.tau[p0, 0]] = v[J]
+    best, pix, null = oracle.coherent(z, idx, tab.U, tab.tau, np.zeros((1, D), np.int32))
+    assert pix[0, 0, 0, 0] == p0
+    assert abs(best[0, 0, 0, 0] - np.sum(np.abs(s) ** 2)) <= 1e-6 * np.sum(np.abs(s) ** 2)
+    assert abs(null[0, 0, 0, 0]) <= 1e-6
+    assert np.isnan(best[1:]).all() and (pix[1:] == -1).all()
+
+
+def test_coherent_two_detectors_has_no_null_space():
+    rng = np.random.default_rng(75)
+    z = _rand_z(rng, 2, 1, 200)
+    tab = synth.sky_tables(76, 2, 10)
+    idx = np.array([[[100]], [[80]]], dtype=np.int32)
+    rc, rn = oracle.coherent_map(z, idx, tab.U, tab.tau, np.zeros((1, 2), np.int32))
+    assert np.all(rn[~np.isnan(rn)] == 0.0)
+    for I, c in ((0, 100), (1, 80)):
+        for p in range(10):
+            s = c + tab.tau[p] - tab.tau[p, I]
+            tot = abs(z[0, 0, s[0]]) ** 2 + abs(z[1, 0, s[1]]) ** 2
+            assert abs(rc[I, 0, 0, 0, p] - tot) <= 1e-6 * tot
+
+
+def test_coherent_noise_statistics():
+    # Gaussian z of unit variance per quadrature: rho_C^2 is chi-square with 4 degrees of
+    # freedom (mean 4), rho_N^2 with 2 N_d - 4 (mean 2 for N_d = 3), at a fixed direction
+    rng = np.random.default_rng(77)
+    D, n = 3, 60_000
+    z = _rand_z(rng, D, 1, n)
+    tab = synth.sky_tables(78, D, 3)
+    pos = np.arange(100, n - 100, 7)
+    idx = np.full((D, 1, len(pos)), -1, dtype=np.int32)
+    idx[0, 0, :] = pos
+    rc, rn = oracle.coherent_map(z, idx, tab.U, tab.tau, np.zeros((1, D), np.int32))
+    mc, mn = np.mean(rc[0, 0, :, 0, :]), np.mean(rn[0, 0, :, 0, :])
+    assert abs(mc - 4.0) < 0.1 and abs(mn - 2.0) < 0.07, (mc, mn)
