@@ -219,6 +219,33 @@ spiir_status spiir_xi2(const float *z, int32_t n_det, int32_t n_templates, int32
                        void *stream);
 
 /*
+ * ---- Coherent search (Section II.C.1, Eq. llr_form; null statistic of the appendix) ----
+ * For every candidate (detector I, template t, window w) at sample c = index[I][t][w],
+ * every time shift k and every sky direction p, detector J contributes
+ *   v_J = z[J][t][s_J],  s_J = c + tau[p][J] - tau[p][I] + shifts[k][(J-I) mod n_det] - shifts[k][0]
+ * (background events shift the other detectors' series relative to the candidate's
+ * detector: column r of the shift table applies to the detector r places after I),
+ * and with the orthogonal matrix U[p] (N_d x N_d, the SVD factor of the noise-weighted
+ * detector response; its first two columns span the signal plane)
+ *   rho_C^2 = sum_{i<2} |sum_J U[p][J][i] v_J|^2,   rho_N^2 = sum_J |v_J|^2 - rho_C^2.
+ * Per (candidate, shift) the direction with the largest rho_C^2 is kept (lowest p on
+ * ties).  Float32 arithmetic.
+ *   z       device complex64 [n_det][n_templates][n], 2 <= n_det <= 8
+ *   index   device int32 [n_det][n_templates][n_win], -1 = no candidate (spiir_triggers)
+ *   U       device float32 [n_pix][n_det][n_det] (row J, column i)
+ *   tau     device int32 [n_pix][n_det]: arrival-time offsets in samples
+ *   shifts  device int32 [n_shift][n_det]: background time shifts by relative detector
+ *           position (all zero: foreground)
+ *   snr2, null2  device float32 [n_det][n_templates][n_win][n_shift]: rho_C^2, rho_N^2
+ *   pix     device int32 same shape: the direction; -1 (and NaN above) where there is no
+ *           candidate or some s_J (any direction) leaves [0, n)
+ */
+spiir_status spiir_coherent(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                            const int32_t *index, int32_t n_win, const float *U, const int32_t *tau,
+                            int32_t n_pix, const int32_t *shifts, int32_t n_shift, float *snr2,
+                            int32_t *pix, float *null2, void *stream);
+
+/*
  * ---- Differentiation (FP32 scan mode only) ----
  * For fitting coefficients to a target response (the overlap of Eq. overlap,
  * Section II.B.1, between a template and the summed filter response).  These

@@ -306,7 +306,9 @@ def coherent_map(z: np.ndarray, index: np.ndarray, U: np.ndarray, tau: np.ndarra
     appendix); a diagonal matrix there would drop the phase coherence.  For the
     candidate of detector I, template t, window w at sample c = index[I, t, w], shift k
     and direction p, detector J contributes v_J = z[J, t, s_J] with
-        s_J = c + tau[p, J] - tau[p, I] + shifts[k, J] - shifts[k, I],
+        s_J = c + tau[p, J] - tau[p, I] + shifts[k, (J - I) mod D] - shifts[k, 0]
+    (background events shift the other detectors' series relative to the candidate's
+    detector, column r of the shift table being the detector r places after it),
     and with U = U[p]:
         rho_C^2 = sum_{i < 2} |sum_J U[J, i] v_J|^2      (projection on the signal plane)
         rho_N^2 = sum_{i >= 2} |sum_J U[J, i] v_J|^2     (projection on the null space).
@@ -325,8 +327,10 @@ def coherent_map(z: np.ndarray, index: np.ndarray, U: np.ndarray, tau: np.ndarra
                 c = int(index[I, t, w])
                 if c < 0:
                     continue
+                rel = [(J - I) % D for J in range(D)]
                 for k in range(K):
-                    s = c + (tau - tau[:, I:I + 1]) + (shifts[k] - shifts[k, I])[None, :]  # [P][D]
+                    sk = np.array([shifts[k, r] - shifts[k, 0] for r in rel])
+                    s = c + (tau - tau[:, I:I + 1]) + sk[None, :]  # [P][D]
                     if s.min() < 0 or s.max() >= n:
                         continue
                     for p in range(P):

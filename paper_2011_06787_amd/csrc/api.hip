@@ -724,6 +724,23 @@ spiir_status spiir_xi2(const float *z, int32_t n_det, int32_t n_templates, int32
     return SPIIR_OK;
 }
 
+spiir_status spiir_coherent(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                            const int32_t *index, int32_t n_win, const float *U, const int32_t *tau,
+                            int32_t n_pix, const int32_t *shifts, int32_t n_shift, float *snr2,
+                            int32_t *pix, float *null2, void *stream) {
+    if (n_det < 2 || n_det > 8) return fail(SPIIR_E_INVAL, "n_det must be in [2, 8]");
+    if (n_templates < 0 || n < 0 || n_win < 0 || n_pix < 0 || n_shift < 0)
+        return fail(SPIIR_E_INVAL, "sizes must be >= 0");
+    if ((int64_t)n_templates * n_win * n_shift == 0) return SPIIR_OK;
+    if (z == nullptr || index == nullptr || shifts == nullptr || snr2 == nullptr ||
+        pix == nullptr || null2 == nullptr || (n_pix > 0 && (U == nullptr || tau == nullptr)))
+        return fail(SPIIR_E_INVAL, "z, index, U, tau, shifts and the outputs must be non-NULL");
+    SPIIR_HIP(spiir::launch_coherent(reinterpret_cast<const float2 *>(z), n_det, n_templates, n, index,
+                                     n_win, U, tau, n_pix, shifts, n_shift, snr2, pix, null2,
+                                     static_cast<hipStream_t>(stream)));
+    return SPIIR_OK;
+}
+
 spiir_status spiir_ckpt_count(const spiir_bank *h, int32_t n, int64_t *n_values) {
     if (h == nullptr || n_values == nullptr) return fail(SPIIR_E_INVAL, "bank or n_values is NULL");
     const spiir::Bank &bk = h->bk;

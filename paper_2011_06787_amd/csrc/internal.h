@@ -170,6 +170,10 @@ hipError_t launch_triggers(const float2 *z, int32_t n_det, int32_t n_templates, 
 hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *z, hipStream_t s);
 hipError_t launch_autocorr(int32_t n_templates, const int32_t *offsets, const float2 *a,
                            const float2 *b, const int32_t *d, int32_t nj, double2 *R, hipStream_t s);
+hipError_t launch_coherent(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
+                           const int32_t *index, int32_t n_win, const float *U, const int32_t *tau,
+                           int32_t n_pix, const int32_t *shifts, int32_t n_shift, float *snr2,
+                           int32_t *pix, float *null2, hipStream_t s);
 hipError_t launch_xi2(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
                       const int32_t *index, int32_t n_win, const double2 *R, int32_t nj, float *xi2,
                       hipStream_t s);

@@ -31,7 +31,7 @@ EXPORTS = (
     "spiir_bank_get_info", "spiir_filter_chunk", "spiir_peaks", "spiir_last_error",
     "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count", "spiir_forward",
     "spiir_backward", "spiir_bank_set_coeffs", "spiir_bank_noise_power", "spiir_triggers",
-    "spiir_bank_autocorr", "spiir_xi2",
+    "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent",
 )
 
 
@@ -105,6 +105,9 @@ def load():
     lib.spiir_bank_autocorr.argtypes = [_P, ctypes.c_int32, _P, _P]
     lib.spiir_xi2.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                               _P, ctypes.c_int32, _P, _P]
+    lib.spiir_coherent.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                   ctypes.c_int32, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P,
+                                   _P, _P, _P]
     lib.spiir_last_error.argtypes = []
     lib.spiir_last_error.restype = ctypes.c_char_p
     for name in ("spiir_bank_create", "spiir_bank_destroy", "spiir_bank_reset",
@@ -409,3 +412,29 @@ def xi2(z, index, R, nj: int, stream=None):
     _check("spiir_xi2", load().spiir_xi2(z.data_ptr(), D, T, n, index.data_ptr(), W, R.data_ptr(),
                                          int(nj), out.data_ptr(), _stream_ptr(stream)))
     return out
+
+
+def coherent(z, index, U, tau, shifts, stream=None):
+    """Coherent and null SNR^2 (Sec. II.C.1) of candidates over sky directions.
+
+    ``z`` cuda complex64 [D][T][n]; ``index`` cuda int32 [D][T][W]; ``U`` cuda float32
+    [P][D][D]; ``tau`` cuda int32 [P][D]; ``shifts`` cuda int32 [K][D].  Returns
+    (rho_C^2, direction, rho_N^2), each [D][T][W][K].
+    """
+    import torch
+    assert z.is_cuda and z.dtype == torch.complex64 and z.is_contiguous() and z.dim() == 3
+    D, T, n = (int(v) for v in z.shape)
+    W = int(index.shape[2])
+    P, K = int(U.shape[0]), int(shifts.shape[0])
+    for a, dt in ((index, torch.int32), (U, torch.float32), (tau, torch.int32), (shifts, torch.int32)):
+        assert a.is_cuda and a.dtype == dt and a.is_contiguous()
+    assert tuple(U.shape) == (P, D, D) and tuple(tau.shape) == (P, D) and shifts.shape[1] == D
+    snr2 = torch.empty((D, T, W, K), dtype=torch.float32, device=z.device)
+    null2 = torch.empty_like(snr2)
+    pix = torch.empty((D, T, W, K), dtype=torch.int32, device=z.device)
+    _check("spiir_coherent", load().spiir_coherent(z.data_ptr(), D, T, n, index.data_ptr(), W,
+                                                   U.data_ptr(), tau.data_ptr(), P,
+                                                   shifts.data_ptr(), K, snr2.data_ptr(),
+                                                   pix.data_ptr(), null2.data_ptr(),
+                                                   _stream_ptr(stream)))
+    return snr2, pix, null2

@@ -278,9 +278,10 @@ def sky_tables(seed: int, n_det: int, n_pix: int, max_offset: int = 44) -> SkyTa
 
 
 def time_shifts(n_det: int, n_shifts: int, step: int = 205) -> np.ndarray:
-    """Background time shifts: shift k (k = 0..n_shifts-1) moves detector J's series by
-    k * step * J samples (detector 0 stays; step 205 samples ~ 0.1 s at 2048 Hz), so shift
-    0 is the unshifted foreground.  int32 [n_shifts][N_d]."""
+    """Background time shifts: in shift k (k = 0..n_shifts-1) the detector r positions
+    after the candidate's own (cyclically) is read k * step * r samples earlier (step 205
+    samples ~ 0.1 s at 2048 Hz), so shift 0 is the unshifted foreground and every shift
+    reads only past data.  int32 [n_shifts][N_d], column r."""
     k = np.arange(n_shifts)[:, None]
-    j = np.arange(n_det)[None, :]
-    return (k * step * j).astype(np.int32)
+    r = np.arange(n_det)[None, :]
+    return (-k * step * r).astype(np.int32)

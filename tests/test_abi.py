@@ -104,6 +104,10 @@ def test_null_and_shape_errors_without_gpu():
     assert lib.spiir_xi2(None, 1, 2, 100, None, 1, None, 0, None, None) == spiir.SPIIR_E_INVAL  # nj 0
     assert lib.spiir_xi2(None, 1, 2, 100, None, 1, None, 5, None, None) == spiir.SPIIR_E_INVAL  # NULLs
     assert lib.spiir_xi2(None, 0, 2, 100, None, 1, None, 5, None, None) == spiir.SPIIR_OK      # empty
+    args = (None, 1, None, None, 4, None, 1, None, None, None, None)
+    assert lib.spiir_coherent(None, 1, 2, 100, *args) == spiir.SPIIR_E_INVAL    # one detector
+    assert lib.spiir_coherent(None, 9, 2, 100, *args) == spiir.SPIIR_E_INVAL    # too many
+    assert lib.spiir_coherent(None, 3, 2, 100, *args) == spiir.SPIIR_E_INVAL    # NULL buffers
     assert lib.spiir_peaks(None, 0, 16, 8, None, None, None) == spiir.SPIIR_OK        # empty no-op
     assert lib.spiir_peaks(None, -1, 16, 8, None, None, None) == spiir.SPIIR_E_INVAL
 

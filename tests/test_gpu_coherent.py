@@ -1,0 +1,93 @@
+"""GPU coherent search (Section II.C.1) against the FP64 oracle.
+
+Inputs are seeded SNR series (synthetic, or the filter bank's output for noise with
+planted coherent signals) and seeded sky tables; both sides read the same arrays.
+rho_C^2 and rho_N^2: 1e-5 relative to the candidate's total power (float32 sums of a
+few terms).  Direction: equal to the oracle's wherever the oracle's best and second
+best rho_C^2 differ by more than 1e-4 relative; elsewhere the GPU's direction must be
+within that band of the oracle maximum.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(gpu_out, z, idx, tab, sh):
+    snr2, pix, null2 = (a.cpu().numpy() for a in gpu_out)
+    rc, rn = oracle.coherent_map(z, idx, tab.U, tab.tau, sh)
+    best, opix, onull = oracle.coherent(z, idx, tab.U, tab.tau, sh)
+    ok = ~np.isnan(best)
+    assert np.array_equal(np.isnan(snr2), ~ok) and np.all(pix[~ok] == -1)
+    assert ok.sum() > 0
+    srt = np.sort(np.where(np.isnan(rc), -np.inf, rc), axis=-1)
+    tot = best + onull
+    with np.errstate(invalid="ignore"):
+        clear = ok & ((srt[..., -1] - srt[..., -2]) > 1e-4 * tot)
+    assert np.array_equal(pix[clear], opix[clear])
+    got = np.take_along_axis(np.where(np.isnan(rc), -np.inf, rc), np.maximum(pix, 0)[..., None], -1)[..., 0]
+    assert np.all(np.abs(got[ok] - best[ok]) <= 1e-4 * tot[ok])
+    assert np.all(np.abs(snr2[ok] - best[ok]) <= 1e-5 * tot[ok])
+    assert np.all(np.abs(null2[ok] - onull[ok]) <= 1e-5 * tot[ok])
+    return ok.sum(), clear.sum()
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_coherent_matches_oracle_on_synthetic_series(gpu, D):
+    import torch
+    from paper_2011_06787_amd import spiir
+    rng = np.random.default_rng(80 + D)
+    T, n, W, P, K = 3, 1200, 4, 300, 3
+    z = ((rng.standard_normal((D, T, n)) + 1j * rng.standard_normal((D, T, n)))).astype(np.complex64)
+    tab = synth.sky_tables(90 + D, D, P)
+    sh = synth.time_shifts(D, K, step=25)
+    idx = rng.integers(200, 900, size=(D, T, W)).astype(np.int32)
+    idx[0, 0, 0] = -1                  # no candidate
+    idx[1, 1, 1] = 30                  # directions reach before the series
+    idx[0, 2, 3] = n - 60              # directions reach past its end
+    idx[2 % D, 0, 1] = 120             # the shifted detectors reach before the series
+    # a planted coherent signal at a known direction for one candidate
+    p0, c = 123, int(idx[0, 1, 2])
+    s = np.array([6.0 + 2.0j, -3.0 + 5.0j])
+    v = tab.U[p0].astype(np.float64)[:, :2] @ s
+    for J in range(D):
+        z[J, 1, c + tab.tau[p0, J] - tab.tau[p0, 0]] += v[J]
+    cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = spiir.coherent(cuda(z), cuda(idx), cuda(tab.U), cuda(tab.tau), cuda(sh))
+    n_ok, n_clear = _compare(out, z, idx, tab, sh)
+    if D >= 3:      # with two detectors every direction's plane is the whole space
+        assert out[1][0, 1, 2, 0].item() == p0
+    print(f"D={D}: {n_ok} evaluations, {n_clear} with a clear best direction")
+
+
+def test_coherent_end_to_end_from_the_filter_bank(gpu):
+    # three detectors' SNR series from the bank (oracle for the oracle side, GPU scan for
+    # the GPU side), candidates from the oracle's trigger selection
+    import torch
+    from paper_2011_06787_amd import spiir
+    rng = np.random.default_rng(95)
+    bank = synth.draw_filters(rng, rng.integers(60, 300, size=8))
+    D, n = 3, 6144
+    x = rng.standard_normal((D, n)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    w = (2.0 / oracle.noise_power(bank)).astype(np.float32)
+    _, idx = oracle.triggers(z_ref.astype(np.complex64), w, 2.5, 1024)
+    tab = synth.sky_tables(96, D, 768)
+    sh = synth.time_shifts(D, 4, step=205)
+    best, opix, onull = oracle.coherent(z_ref, idx, tab.U, tab.tau, sh)
+    with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=n) as sb:
+        z, _, _ = sb.filter_chunk(torch.from_numpy(x).cuda())
+        cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        snr2, pix, null2 = (a.cpu().numpy() for a in spiir.coherent(z, cuda(idx), cuda(tab.U),
+                                                                     cuda(tab.tau), cuda(sh)))
+    ok = ~np.isnan(best)
+    assert ok.sum() > 20 and np.array_equal(np.isnan(snr2), ~ok)
+    tot = best + onull
+    # the series differ by the FP32 scan's error (~1e-6 relative): 1e-4 of the total power
+    assert np.all(np.abs(snr2[ok] - best[ok]) <= 1e-4 * tot[ok])
+    agree = np.mean(pix[ok] == opix[ok])
+    print(f"end to end: {ok.sum()} evaluations, direction agreement {agree:.3f}")
+    assert agree >= 0.95

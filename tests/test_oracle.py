@@ -529,6 +529,7 @@ def test_coherent_plus_null_is_total_power():
     tab = synth.sky_tables(72, D, 40)
     sh = synth.time_shifts(D, 2, step=20)
     idx = np.array([[[150, 220]] * T] * D, dtype=np.int32)
+    assert np.all(sh[:, 0] == 0) and np.all(sh[1, 1:] < 0)      # past data only
     rc, rn = oracle.coherent_map(z, idx, tab.U, tab.tau, sh)
     for I in range(D):
         for t in range(T):
@@ -536,7 +537,8 @@ def test_coherent_plus_null_is_total_power():
                 c = idx[I, t, w]
                 for k in range(2):
                     for p in range(40):
-                        s = c + tab.tau[p] - tab.tau[p, I] + sh[k] - sh[k, I]
+                        rel = [(J - I) % D for J in range(D)]
+                        s = c + tab.tau[p] - tab.tau[p, I] + sh[k][rel] - sh[k, 0]
                         tot = sum(abs(z[J, t, s[J]]) ** 2 for J in range(D))
                         assert abs(rc[I, t, w, k, p] + rn[I, t, w, k, p] - tot) <= 1e-6 * tot
 
