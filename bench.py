@@ -82,6 +82,8 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="batching: skip the autotuner")
     p.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
     p.add_argument("--diff-only", action="store_true")
+    p.add_argument("--diff-filters-per-lane", type=int, default=2,
+                   help="differentiation bank: filters per lane (2: 1024 waves for the 131k filters)")
     p.add_argument("--no-xi2", action="store_true", help="skip the signal-consistency section")
     p.add_argument("--no-coherent", action="store_true", help="skip the coherent-search section")
     p.add_argument("--coherent-only", action="store_true")
@@ -253,7 +255,8 @@ def differentiation_run(args, dev):
     target = synth.chirp_targets(0, bank.n_templates, n)
     x = torch.from_numpy(w.input()).to(dev)
     g = torch.from_numpy(target).to(dev)
-    sb = spiir.SpiirBank.from_bank(bank, max_chunk=n, ckpt_stride=2048)
+    sb = spiir.SpiirBank.from_bank(bank, max_chunk=n, ckpt_stride=2048,
+                                   filters_per_lane=args.diff_filters_per_lane)
     a = torch.from_numpy(bank.a).to(dev)
     b = torch.from_numpy(bank.b).to(dev)
     sb.set_coeffs(a, b)

@@ -149,9 +149,12 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
     }
 }
 
-// One workgroup of kStateWaves waves per (kStateWaves consecutive tiles, detector);
-// wave w owns tile blockIdx.x*kStateWaves + w (16 filters).  For every chunk of kChunk
-// blocks the workgroup stages the input range all its tiles read,
+// One workgroup of kStateWaves waves per kStateWaves consecutive tiles; wave w owns
+// tile blockIdx.x*kStateWaves + w (16 filters) for every detector in turn.  The
+// tile's W' fragments of its first kACache K steps (nearly every tile has fewer than
+// that) are loaded into registers once and serve every chunk of every detector;
+// further steps stream from memory.  For every chunk of kChunk blocks the workgroup
+// stages the input range all its tiles read,
 //     x[c0 L + P_lo, (c0 + kChunk - 1) L + P_hi)     (P_lo, P_hi: union band of the tiles)
 // once into LDS (hi and lo planes), skewed by 8 elements per row of L so that the
 // 16-byte fragments of consecutive blocks (columns) start 4 banks apart; the MFMA B
@@ -161,6 +164,7 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
 // two uses and several workgroups share a CU.
 constexpr int kStateWaves = 4;
 constexpr int kSlFloats = 32 * (kChunk + 1);   // one wave's S rows
+constexpr int kACache = 8;                    // W' K steps kept in registers
 
 __device__ __forceinline__ int skew(int p, int L) { return p + 8 * (p / L); }
 
@@ -175,11 +179,11 @@ __global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
     __shared__ C2<float> tot32[kStateWaves][4][16];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    const int det = blockIdx.y;
     const int tile0 = blockIdx.x * kStateWaves;
     const int tile_id = tile0 + wave;
     const bool active = tile_id < n_tiles;
-    const WTile tl = tiles[active ? tile_id : tile0];
+    WTile tl = tiles[active ? tile_id : tile0];
+    tl.nks = __builtin_amdgcn_readfirstlane(tl.nks);
     const BTemplate bt = tmpls[tl.tmpl];
     // union band of the workgroup's tiles (multiples of 16)
     int p_lo = 1 << 30, p_hi = -(1 << 30);
@@ -188,8 +192,6 @@ __global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
         p_lo = min(p_lo, tw.sigma_lo);
         p_hi = max(p_hi, tw.sigma_lo + 16 * tw.nks);
     }
-    const uint16_t *xh = xs + (int64_t)det * xs_stride + hist_pad;
-    const uint16_t *xl = xh + (int64_t)n_det * xs_stride;
     uint16_t *sh = lds;
     uint16_t *slo = lds + xwin;
     float(*sl)[kChunk + 1] =
@@ -197,76 +199,98 @@ __global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
     const int col = lane % 32;
     const int kg = (lane / 32) * 8;
     const uint16_t *ap = wa + tl.a_off + (lane % 32) * 16 + kg;
+    bf16x8 ach[kACache], acl[kACache];
+#pragma unroll
+    for (int ks = 0; ks < kACache; ++ks) {
+        if (active && ks < tl.nks) {
+            ach[ks] = load8(ap + (int64_t)ks * 1024);
+            acl[ks] = load8(ap + (int64_t)ks * 1024 + 512);
+        } else {
+            ach[ks] = bf16x8{};
+            acl[ks] = bf16x8{};
+        }
+    }
 
     const int f = lane & 15;
     const int q = lane >> 4;
     const int64_t gf = tl.g0 + f;
-    const double2 ys = active ? state[(int64_t)det * n_fpad + gf] : make_double2(0.0, 0.0);
     const double2 ta = active ? aL[gf] : make_double2(0.0, 0.0);
     const bool long_pole = active && lp[gf] != 0;
-    C2<double> y64{ys.x, ys.y};
-    C2<float> y32{(float)ys.x, (float)ys.y};
     const C2<double> A64{ta.x, ta.y};
     const C2<float> A32{(float)ta.x, (float)ta.y};
     const int64_t row_len2 = bt.fpad;
-    uint32_t *yh = reinterpret_cast<uint32_t *>(yt + (int64_t)det * y_per_det + bt.y_off) + tl.f0 + f;
-    uint32_t *yl = reinterpret_cast<uint32_t *>(yt + (int64_t)(n_det + det) * y_per_det + bt.y_off) +
-                   tl.f0 + f;
 
-    for (int c0 = 0; c0 < nb; c0 += kChunk) {
-        const int cols = min(kChunk, nb - c0);
-        const int span = (cols - 1) * L + (p_hi - p_lo);   // multiple of 16
-        const int64_t g0 = (int64_t)c0 * L + p_lo;
-        __syncthreads();   // previous chunk's S rows no longer read
-        for (int e = threadIdx.x; e < span / 8 * 2; e += blockDim.x) {
-            const int plane = e & 1;
-            const int pp = (e >> 1) * 8;
-            const bf16x8 v = load8((plane ? xl : xh) + g0 + pp);
-            *reinterpret_cast<bf16x8 *>((plane ? slo : sh) + skew(pp, L)) = v;
-        }
-        __syncthreads();
-        f32x16 acc[2] = {};
-        if (active) {
-            bool valid[2];
-            int rel[2];
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-                const int b = ct * 32 + col;
-                valid[ct] = b < cols;
-                rel[ct] = (valid[ct] ? b : 0) * L + tl.sigma_lo - p_lo + kg;
+    for (int det = 0; det < n_det; ++det) {
+        const uint16_t *xh = xs + (int64_t)det * xs_stride + hist_pad;
+        const uint16_t *xl = xh + (int64_t)n_det * xs_stride;
+        const double2 ys = active ? state[(int64_t)det * n_fpad + gf] : make_double2(0.0, 0.0);
+        C2<double> y64{ys.x, ys.y};
+        C2<float> y32{(float)ys.x, (float)ys.y};
+        uint32_t *yh =
+            reinterpret_cast<uint32_t *>(yt + (int64_t)det * y_per_det + bt.y_off) + tl.f0 + f;
+        uint32_t *yl = reinterpret_cast<uint32_t *>(yt + (int64_t)(n_det + det) * y_per_det +
+                                                    bt.y_off) + tl.f0 + f;
+        for (int c0 = 0; c0 < nb; c0 += kChunk) {
+            const int cols = min(kChunk, nb - c0);
+            const int span = (cols - 1) * L + (p_hi - p_lo);   // multiple of 16
+            const int64_t g0 = (int64_t)c0 * L + p_lo;
+            __syncthreads();   // previous chunk's S rows no longer read
+            for (int e = threadIdx.x; e < span / 8 * 2; e += blockDim.x) {
+                const int plane = e & 1;
+                const int pp = (e >> 1) * 8;
+                const bf16x8 v = load8((plane ? xl : xh) + g0 + pp);
+                *reinterpret_cast<bf16x8 *>((plane ? slo : sh) + skew(pp, L)) = v;
             }
-            for (int ks = 0; ks < tl.nks; ++ks) {
-                const bf16x8 ah = load8(ap + (int64_t)ks * 1024);
-                const bf16x8 al = load8(ap + (int64_t)ks * 1024 + 512);
+            __syncthreads();
+            f32x16 acc[2] = {};
+            if (active) {
+                bool valid[2];
+                int rel[2];
 #pragma unroll
                 for (int ct = 0; ct < 2; ++ct) {
-                    bf16x8 bh = {}, bl = {};
-                    if (valid[ct]) {
-                        const int o = skew(rel[ct] + 16 * ks, L);
-                        bh = *reinterpret_cast<const bf16x8 *>(sh + o);
-                        bl = *reinterpret_cast<const bf16x8 *>(slo + o);
+                    const int b = ct * 32 + col;
+                    valid[ct] = b < cols;
+                    rel[ct] = (valid[ct] ? b : 0) * L + tl.sigma_lo - p_lo + kg;
+                }
+                auto step = [&](int ks, const bf16x8 &ah, const bf16x8 &al) {
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct) {
+                        bf16x8 bh = {}, bl = {};
+                        if (valid[ct]) {
+                            const int o = skew(rel[ct] + 16 * ks, L);
+                            bh = *reinterpret_cast<const bf16x8 *>(sh + o);
+                            bl = *reinterpret_cast<const bf16x8 *>(slo + o);
+                        }
+                        acc[ct] = mma3(ah, al, bh, bl, acc[ct]);
                     }
-                    acc[ct] = mma3(ah, al, bh, bl, acc[ct]);
+                };
+#pragma unroll
+                for (int ks = 0; ks < kACache; ++ks)
+                    if (ks < tl.nks) step(ks, ach[ks], acl[ks]);
+                for (int ks = kACache; ks < tl.nks; ++ks) {
+                    const bf16x8 ah = load8(ap + (int64_t)ks * 1024);
+                    const bf16x8 al = load8(ap + (int64_t)ks * 1024 + 512);
+                    step(ks, ah, al);
                 }
             }
-        }
-        __syncthreads();   // staged input no longer read: the LDS now holds S rows
-        if (active) {
+            __syncthreads();   // staged input no longer read: the LDS now holds S rows
+            if (active) {
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
+                for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    sl[8 * (i / 4) + 4 * (lane / 32) + (i % 4)][ct * 32 + col] = acc[ct][i];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            if (long_pole)
-                carry_chunk<double>(sl, tot64[wave], f, q, cols, A64, y64, yh, yl, row_len2, c0);
-            else
-                carry_chunk<float>(sl, tot32[wave], f, q, cols, A32, y32, yh, yl, row_len2, c0);
+                    for (int i = 0; i < 16; ++i)
+                        sl[8 * (i / 4) + 4 * (lane / 32) + (i % 4)][ct * 32 + col] = acc[ct][i];
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                if (long_pole)
+                    carry_chunk<double>(sl, tot64[wave], f, q, cols, A64, y64, yh, yl, row_len2, c0);
+                else
+                    carry_chunk<float>(sl, tot32[wave], f, q, cols, A32, y32, yh, yl, row_len2, c0);
+            }
         }
+        if (active && q == 0)
+            state[(int64_t)det * n_fpad + gf] =
+                long_pole ? make_double2(y64.r, y64.i) : make_double2((double)y32.r, (double)y32.i);
     }
-    if (active && q == 0)
-        state[(int64_t)det * n_fpad + gf] =
-            long_pole ? make_double2(y64.r, y64.i) : make_double2((double)y32.r, (double)y32.i);
 }
 
 // Output product, one workgroup of (2L/64) waves per (template, 128 columns); a
@@ -316,12 +340,30 @@ __global__ __launch_bounds__(512) void block_output_kernel(
         return xs + (int64_t)plane * n_det * xs_stride + (int64_t)det * xs_stride + hist_pad +
                (int64_t)blk * L + bt.sigma_lo + 16 * (ks - bt.nks_p) + 8 * half;
     };
-    const int n_b_items = kOutCols * 2 * 2;   // (column, plane, half) 16-byte items per step
-    auto stage = [&](int ks, int buf) {
-        for (int e = tid; e < n_b_items; e += nthreads) {
-            const int c = e >> 2, plane = (e >> 1) & 1, half = e & 1;
-            const bf16x8 v = load8(b_src(ks, c, plane, half));
-            *reinterpret_cast<bf16x8 *>(&bs[buf][plane][c * kBPitch + 8 * half]) = v;
+    // (column, plane, half) 16-byte items per step; a thread owns at most kBItems of them
+    // (128 threads at L = 64 for 512 items).  The global loads of the next step are issued
+    // before the current step's products and written to LDS after them, so their latency
+    // hides behind the matrix-core work.
+    constexpr int kBItems = 4;
+    const int n_b_items = kOutCols * 2 * 2;
+    auto stage_load = [&](int ks, bf16x8 (&v)[kBItems]) {
+#pragma unroll
+        for (int i = 0; i < kBItems; ++i) {
+            const int e = tid + i * nthreads;
+            if (e < n_b_items) {
+                const int c = e >> 2, plane = (e >> 1) & 1, half = e & 1;
+                v[i] = load8(b_src(ks, c, plane, half));
+            }
+        }
+    };
+    auto stage_store = [&](int buf, const bf16x8 (&v)[kBItems]) {
+#pragma unroll
+        for (int i = 0; i < kBItems; ++i) {
+            const int e = tid + i * nthreads;
+            if (e < n_b_items) {
+                const int c = e >> 2, plane = (e >> 1) & 1, half = e & 1;
+                *reinterpret_cast<bf16x8 *>(&bs[buf][plane][c * kBPitch + 8 * half]) = v[i];
+            }
         }
     };
     auto a_ptr = [&](int ks, int r) -> const uint16_t * {
@@ -336,7 +378,9 @@ __global__ __launch_bounds__(512) void block_output_kernel(
 
     bf16x8 ah[2], al[2];
     if (nks > 0) {
-        stage(0, 0);
+        bf16x8 v0[kBItems];
+        stage_load(0, v0);
+        stage_store(0, v0);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             ah[r] = load8(a_ptr(0, r));
@@ -347,7 +391,7 @@ __global__ __launch_bounds__(512) void block_output_kernel(
     for (int ks = 0; ks < nks; ++ks) {
         const int buf = ks & 1;
         // prefetch the next step: A into registers, B into the other LDS buffer
-        bf16x8 nh[2], nl[2];
+        bf16x8 nh[2], nl[2], nb[kBItems];
         const bool more = ks + 1 < nks;
         if (more) {
 #pragma unroll
@@ -355,7 +399,7 @@ __global__ __launch_bounds__(512) void block_output_kernel(
                 nh[r] = load8(a_ptr(ks + 1, r));
                 nl[r] = load8(a_ptr(ks + 1, r) + 512);
             }
-            stage(ks + 1, buf ^ 1);
+            stage_load(ks + 1, nb);
         }
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
@@ -366,6 +410,7 @@ __global__ __launch_bounds__(512) void block_output_kernel(
             for (int r = 0; r < 2; ++r) acc[r][ct] = mma3(ah[r], al[r], bh, bl, acc[r][ct]);
         }
         if (more) {
+            stage_store(buf ^ 1, nb);
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 ah[r] = nh[r];
@@ -430,7 +475,7 @@ hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *
     if (bk.n_wtiles > 0) {
         const int32_t xwin = block_state_xwin(bk);
         hipLaunchKernelGGL(block_state_kernel,
-                           dim3((bk.n_wtiles + kStateWaves - 1) / kStateWaves, bk.n_det),
+                           dim3((bk.n_wtiles + kStateWaves - 1) / kStateWaves),
                            dim3(kWave * kStateWaves), block_state_lds_bytes(bk), s,
                            bk.d_wtiles, bk.n_wtiles, bk.d_btmpl, bk.d_wa, bk.d_xs, bk.xs_stride,
                            bk.hist_pad, bk.n_det, L, nb, bk.d_aL, bk.d_lp, bk.d_state64, bk.n_fpad,
