@@ -71,6 +71,7 @@ __global__ void split_input_kernel(const float *__restrict__ x, int32_t n,
 // totals are combined through LDS (Ystart[q+1] = A^len Ystart[q] + T[q]), and each
 // lane then adds A^c Ystart[q] to its local states.  The state entering every block
 // is written as bf16 hi + lo.  R is double for long-pole filters, float otherwise.
+// AG = A^kGroup (precomputed per filter).
 constexpr int kChunk = 64;
 constexpr int kGroup = kChunk / 4;
 
@@ -104,9 +105,9 @@ __device__ __forceinline__ void store_split(uint32_t *yh, uint32_t *yl, float yr
 
 template <typename R>
 __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R> (*tot)[16],
-                                            int f, int q, int valid_cols, C2<R> A, C2<R> &y_prev,
-                                            uint32_t *yh, uint32_t *yl, int64_t row_len2,
-                                            int64_t col0) {
+                                            int f, int q, int valid_cols, C2<R> A, C2<R> AG,
+                                            C2<R> &y_prev, uint32_t *yh, uint32_t *yl,
+                                            int64_t row_len2, int64_t col0) {
     // local scan of the group from zero
     const int c_lo = q * kGroup;
     const int len = max(0, min(kGroup, valid_cols - c_lo));
@@ -129,8 +130,11 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
 #pragma unroll
     for (int qq = 0; qq < 4; ++qq) {
         const int lq = max(0, min(kGroup, valid_cols - qq * kGroup));
-        C2<R> p{1, 0};
-        for (int k = 0; k < lq; ++k) p = cmul(p, A);   // A^lq
+        C2<R> p = AG;                                  // A^kGroup for a full group
+        if (lq < kGroup) {
+            p = C2<R>{1, 0};
+            for (int k = 0; k < lq; ++k) p = cmul(p, A);   // A^lq (last chunk only)
+        }
         if (qq == q) ystart = ynext;
         ynext = cfma(p, ynext, tot[qq][f]);
     }
@@ -218,6 +222,10 @@ __global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
     const bool long_pole = active && lp[gf] != 0;
     const C2<double> A64{ta.x, ta.y};
     const C2<float> A32{(float)ta.x, (float)ta.y};
+    C2<double> AG64{1.0, 0.0};
+    for (int k = 0; k < kGroup; ++k) AG64 = cmul(AG64, A64);
+    C2<float> AG32{1.0f, 0.0f};
+    for (int k = 0; k < kGroup; ++k) AG32 = cmul(AG32, A32);
     const int64_t row_len2 = bt.fpad;
 
     for (int det = 0; det < n_det; ++det) {
@@ -282,9 +290,11 @@ __global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
                         sl[8 * (i / 4) + 4 * (lane / 32) + (i % 4)][ct * 32 + col] = acc[ct][i];
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 if (long_pole)
-                    carry_chunk<double>(sl, tot64[wave], f, q, cols, A64, y64, yh, yl, row_len2, c0);
+                    carry_chunk<double>(sl, tot64[wave], f, q, cols, A64, AG64, y64, yh, yl,
+                                        row_len2, c0);
                 else
-                    carry_chunk<float>(sl, tot32[wave], f, q, cols, A32, y32, yh, yl, row_len2, c0);
+                    carry_chunk<float>(sl, tot32[wave], f, q, cols, A32, AG32, y32, yh, yl,
+                                       row_len2, c0);
             }
         }
         if (active && q == 0)
