@@ -82,8 +82,8 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="batching: skip the autotuner")
     p.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
     p.add_argument("--diff-only", action="store_true")
-    p.add_argument("--diff-filters-per-lane", type=int, default=2,
-                   help="differentiation bank: filters per lane (2: 1024 waves for the 131k filters)")
+    p.add_argument("--diff-filters-per-lane", type=int, default=4,
+                   help="differentiation bank: filters per lane")
     p.add_argument("--no-xi2", action="store_true", help="skip the signal-consistency section")
     p.add_argument("--no-coherent", action="store_true", help="skip the coherent-search section")
     p.add_argument("--coherent-only", action="store_true")

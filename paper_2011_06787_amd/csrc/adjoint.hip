@@ -14,6 +14,18 @@
 // segment a forward sweep keeps the state at the start of every 128-sample block
 // (LDS), each block is re-swept keeping the state at every 16-sample sub-block
 // (registers), and each sub-block is recomputed into registers and walked backward.
+//
+// Segments in parallel (signals of several checkpoint segments): the adjoint is a
+// linear recurrence, so inside segment s = [b, e] it splits as
+//     lambda[n] = lambda_s[n] + conj(a)^(e+1-n) Lambda_s,   Lambda_s = lambda[e+1],
+// lambda_s being the same recurrence started from zero at e.  Every (slice, detector,
+// segment) workgroup then walks its segment independently and returns
+//     GA_s = sum lambda_s[n] conj(y[n-1]),   EA_s = sum conj(a)^(e+1-n) conj(y[n-1]),
+//     GB_s = sum lambda_s[n] x[n-d],         EB_s = sum conj(a)^(e+1-n) x[n-d],
+//     L0_s = lambda_s[b],                    W_s  = conj(a)^(e+1-b),
+// and a per-filter pass joins them from the last segment down:
+//     grad_a += GA_s + Lambda_s EA_s,  grad_b += GB_s + Lambda_s EB_s,
+//     Lambda_{s-1} = L0_s + W_s Lambda_s   (Lambda of the last segment = 0).
 #include <algorithm>
 
 #include "internal.h"
@@ -33,13 +45,18 @@ __device__ __forceinline__ Cx step(Cx y, float ar, float ai, float br, float bi,
     return Cx{fmaf(ar, y.r, fmaf(-ai, y.i, br * xv)), fmaf(ar, y.i, fmaf(ai, y.r, bi * xv))};
 }
 
+// SPLIT = false: one workgroup per slice walks every detector and segment in turn
+// and writes the gradients.  SPLIT = true: one workgroup per (slice, segment,
+// detector) = (blockIdx.x, blockIdx.y, blockIdx.z) writes its six partial sums to
+// `part` ([det][seg][6][lanes]) for join_kernel.
+template <bool SPLIT>
 __global__ __launch_bounds__(512) void backward_kernel(
     const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
     const int32_t *__restrict__ perm, const Slice *__restrict__ slices, int64_t lanes_total,
     const float *__restrict__ x, int32_t n, int32_t n_det, int32_t hist_len,
     const float2 *__restrict__ gz, int32_t n_templates, const float2 *__restrict__ ckpt,
     int32_t stride, int32_t n_seg, float2 *__restrict__ grad_a, float2 *__restrict__ grad_b,
-    int32_t win_floats) {
+    int32_t win_floats, float2 *__restrict__ part) {
     extern __shared__ float smem[];
     float *win = smem;
     const int wave = threadIdx.x / kWave;
@@ -59,11 +76,21 @@ __global__ __launch_bounds__(512) void backward_kernel(
     const int base = hist_len - d;   // window index of x[seg_start - d]
     float gar = 0.f, gai = 0.f, gbr = 0.f, gbi = 0.f;
 
-    for (int det = 0; det < n_det; ++det) {
+    const int det_lo = SPLIT ? (int)blockIdx.z : 0, det_hi = SPLIT ? det_lo + 1 : n_det;
+    for (int det = det_lo; det < det_hi; ++det) {
         const float *xd = x + (int64_t)det * n;
         const float2 *gt = gz + ((int64_t)det * n_templates + sl.tmpl) * n;
         float lr = 0.f, li = 0.f;   // lambda_k[n+1]
-        for (int seg = n_seg - 1; seg >= 0; --seg) {
+        const int seg_hi = SPLIT ? (int)blockIdx.y : n_seg - 1;
+        const int seg_lo = SPLIT ? (int)blockIdx.y : 0;
+        for (int seg = seg_hi; seg >= seg_lo; --seg) {
+            // SPLIT: lambda restarts from zero at the segment end; w = conj(a)^(e+1-n)
+            float wr = 1.f, wi = 0.f, ear = 0.f, eai = 0.f, ebr = 0.f, ebi = 0.f;
+            if (SPLIT) {
+                lr = 0.f;
+                li = 0.f;
+                gar = gai = gbr = gbi = 0.f;
+            }
             const int s0 = seg * stride;
             const int len = min(stride, n - s0);
             __syncthreads();   // previous window no longer read
@@ -131,11 +158,32 @@ __global__ __launch_bounds__(512) void backward_kernel(
                         const float xv = xp[i];
                         gbr = fmaf(lr, xv, gbr);
                         gbi = fmaf(li, xv, gbi);
+                        if (SPLIT) {
+                            // w <- w conj(a); EA += w conj(y[n-1]); EB += w x[n-d]
+                            const float nwr = fmaf(wr, ar, wi * ai);
+                            const float nwi = fmaf(wi, ar, -wr * ai);
+                            wr = nwr;
+                            wi = nwi;
+                            ear = fmaf(wr, yp.r, fmaf(wi, yp.i, ear));
+                            eai = fmaf(wi, yp.r, fmaf(-wr, yp.i, eai));
+                            ebr = fmaf(wr, xv, ebr);
+                            ebi = fmaf(wi, xv, ebi);
+                        }
                     }
                 }
             }
+            if (SPLIT) {
+                float2 *pp = part + ((int64_t)det * n_seg + seg) * 6 * lanes_total + g;
+                pp[0 * lanes_total] = make_float2(gar, gai);
+                pp[1 * lanes_total] = make_float2(gbr, gbi);
+                pp[2 * lanes_total] = make_float2(ear, eai);
+                pp[3 * lanes_total] = make_float2(ebr, ebi);
+                pp[4 * lanes_total] = make_float2(lr, li);
+                pp[5 * lanes_total] = make_float2(wr, wi);
+            }
         }
     }
+    if (SPLIT) return;
     if (active) {
         const int32_t k = perm[g];
         if (k >= 0) {
@@ -158,6 +206,37 @@ __global__ void set_coeffs_kernel(const int32_t *__restrict__ perm, const float2
     }
 }
 
+// Joins the segments' partial sums of every filter (see the header): one thread per
+// lane of the scan layout, detectors summed, gradients written through perm.
+__global__ void join_kernel(const float2 *__restrict__ part, const int32_t *__restrict__ perm,
+                            int64_t lanes, int32_t n_det, int32_t n_seg,
+                            float2 *__restrict__ grad_a, float2 *__restrict__ grad_b) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < lanes;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = perm[g];
+        if (k < 0) continue;
+        float gar = 0.f, gai = 0.f, gbr = 0.f, gbi = 0.f;
+        for (int det = 0; det < n_det; ++det) {
+            float Lr = 0.f, Li = 0.f;   // Lambda of the segment
+            for (int seg = n_seg - 1; seg >= 0; --seg) {
+                const float2 *pp = part + ((int64_t)det * n_seg + seg) * 6 * lanes + g;
+                const float2 ga = pp[0], gb = pp[lanes], ea = pp[2 * lanes], eb = pp[3 * lanes];
+                const float2 l0 = pp[4 * lanes], w = pp[5 * lanes];
+                gar += ga.x + (Lr * ea.x - Li * ea.y);
+                gai += ga.y + (Lr * ea.y + Li * ea.x);
+                gbr += gb.x + (Lr * eb.x - Li * eb.y);
+                gbi += gb.y + (Lr * eb.y + Li * eb.x);
+                const float nr = l0.x + (w.x * Lr - w.y * Li);
+                const float ni = l0.y + (w.x * Li + w.y * Lr);
+                Lr = nr;
+                Li = ni;
+            }
+        }
+        grad_a[k] = make_float2(gar, gai);
+        grad_b[k] = make_float2(gbr, gbi);
+    }
+}
+
 }  // namespace
 
 size_t backward_lds_bytes(int32_t stride, int32_t hist_len, int32_t fpl) {
@@ -167,9 +246,12 @@ size_t backward_lds_bytes(int32_t stride, int32_t hist_len, int32_t fpl) {
 }
 
 hipError_t prepare_backward(const Bank &bk) {
-    return hipFuncSetAttribute((const void *)backward_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl));
+    const int lds = (int)backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl);
+    hipError_t e = hipFuncSetAttribute((const void *)backward_kernel<false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)backward_kernel<true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 hipError_t launch_backward(const Bank &bk, const float *x, int32_t n, const float2 *gz,
@@ -178,11 +260,22 @@ hipError_t launch_backward(const Bank &bk, const float *x, int32_t n, const floa
     if (n <= 0 || bk.n_slices == 0) return hipSuccess;
     const int32_t n_seg = (n + bk.ckpt_stride - 1) / bk.ckpt_stride;
     const int32_t win_floats = ((bk.ckpt_stride + bk.hist_len + kSub) + 3) & ~3;
-    hipLaunchKernelGGL(backward_kernel, dim3(bk.n_slices), dim3(kWave * bk.fpl),
-                       backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl), s, bk.d_a, bk.d_b,
-                       bk.d_delay, bk.d_perm, bk.d_slices, bk.n_slots * kWave, x, n, bk.n_det,
-                       bk.hist_len, gz, bk.n_templates, ckpt, bk.ckpt_stride, n_seg, grad_a, grad_b,
-                       win_floats);
+    const int64_t lanes = bk.n_slots * kWave;
+    const size_t lds = backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl);
+    if (n_seg > 1 && bk.d_bwd_part != nullptr && n_seg <= bk.bwd_max_seg) {
+        hipLaunchKernelGGL(backward_kernel<true>, dim3(bk.n_slices, n_seg, bk.n_det),
+                           dim3(kWave * bk.fpl), lds, s, bk.d_a, bk.d_b, bk.d_delay, bk.d_perm,
+                           bk.d_slices, lanes, x, n, bk.n_det, bk.hist_len, gz, bk.n_templates, ckpt,
+                           bk.ckpt_stride, n_seg, grad_a, grad_b, win_floats, bk.d_bwd_part);
+        const int64_t blocks = std::min<int64_t>((lanes + 255) / 256, 8192);
+        hipLaunchKernelGGL(join_kernel, dim3((unsigned)blocks), dim3(256), 0, s, bk.d_bwd_part,
+                           bk.d_perm, lanes, bk.n_det, n_seg, grad_a, grad_b);
+    } else {
+        hipLaunchKernelGGL(backward_kernel<false>, dim3(bk.n_slices), dim3(kWave * bk.fpl), lds, s,
+                           bk.d_a, bk.d_b, bk.d_delay, bk.d_perm, bk.d_slices, lanes, x, n,
+                           bk.n_det, bk.hist_len, gz, bk.n_templates, ckpt, bk.ckpt_stride, n_seg,
+                           grad_a, grad_b, win_floats, nullptr);
+    }
     return hipGetLastError();
 }
 

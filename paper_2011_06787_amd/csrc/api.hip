@@ -450,6 +450,12 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
                     st = fail(SPIIR_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
             }
             if (st == SPIIR_OK && bk.balanced) st = plan_balanced(bk, s);
+            // per-segment partial sums of the adjoint, when a signal can span several
+            // checkpoint segments (the segments are then walked in parallel)
+            bk.bwd_max_seg = (bk.max_chunk + bk.ckpt_stride - 1) / bk.ckpt_stride;
+            if (st == SPIIR_OK && bk.bwd_max_seg > 1)
+                st = dev_alloc(bk, &bk.d_bwd_part,
+                               (int64_t)bk.n_det * bk.bwd_max_seg * 6 * bk.n_slots * spiir::kWave);
             if (st == SPIIR_OK) st = zero_queue(bk, s);
         }
         if (st == SPIIR_OK) st = zero_stream_state(bk, s);

@@ -92,6 +92,7 @@ struct Bank {
     int32_t balance_lds = 0;     // dynamic LDS per workgroup of the balanced scan (bytes)
     int32_t n_splits = 0;        // slices cut between two waves (per detector)
     int32_t ckpt_stride = 2048;  // differentiation: samples per checkpoint segment
+    int32_t bwd_max_seg = 0;     // segments of a max_chunk signal (adjoint partial sums sized for it)
 
     // FP32 scan layout
     int32_t n_slices = 0;
@@ -111,6 +112,7 @@ struct Bank {
     int32_t *d_seg_off = nullptr;      // [balance_waves+1]: list of wave w is [off[w], off[w+1])
     uint32_t *d_split_flags = nullptr; // [D][n_splits]: launches whose first part has published
     ScanQueue *d_bqueue = nullptr;     // balanced schedule: launch epoch, finished waves, timeouts
+    float2 *d_bwd_part = nullptr;      // adjoint per-segment sums [D][bwd_max_seg][6][lanes]
     std::vector<int32_t> h_slice_slots;  // slots of every slice (host copy, for planning)
     int32_t *d_order = nullptr;  // [D*n_slices]: det*n_slices + slice, largest slices first
     int32_t *d_slice_order = nullptr;  // [n_slices]: slices, largest first

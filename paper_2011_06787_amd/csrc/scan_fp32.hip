@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     const int32_t *__restrict__ slice_order, int32_t n_slices,
     int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
     int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, int32_t tile_len,
-    int32_t win_floats, float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg) {
+    float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg) {
     extern __shared__ float smem[];
     float *win = smem;
     // wave-uniform values live in scalar registers (readfirstlane), so that the
@@ -478,12 +478,8 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
 // (largest slices first inside a tile) by an atomic counter, one item per wave at
 // a time, so every SIMD gets an equal share however uneven the slices are.  An
 // item needs the state its slice reached at the end of the previous tile, which
-// another wave, possibly on another XCD, produced.  The hand-off avoids cache-wide
-// operations: the carried state is written and read with device-scope atomic
-// accesses (coherent across XCDs, not kept in the non-coherent caches); the
-// producer waits for those stores to complete before it advances the slice's flag
-// (a device-scope atomic), and the consumer spins on the flag before it loads the
-// state.  Items are handed out in order, so the producer of any awaited item is
+// another wave, possibly on another XCD, produced: it is handed over as described
+// above (coherent state accesses, a flag, a bounded wait).  Items are handed out in order, so the producer of any awaited item is
 // already running and the wait ends; it is bounded all the same, and a wait that
 // hits the bound is counted in ScanQueue::error.  Flags count tiles since the bank
 // was created: a launch knows the count every slice reached before it (`epoch`),
@@ -495,7 +491,7 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
     float2 *__restrict__ state, const Slice *__restrict__ slices, const int32_t *__restrict__ order,
     int32_t n_slices, int32_t n_det, int64_t lanes_total, const float *__restrict__ x, int32_t n,
     const float *__restrict__ hist, int32_t hist_len, float2 *__restrict__ partial,
-    int32_t part_stride, int32_t tile, int32_t win_floats, ScanQueue *__restrict__ queue,
+    int32_t part_stride, int32_t tile, ScanQueue *__restrict__ queue,
     uint32_t *__restrict__ flags) {
     extern __shared__ float smem[];
     float *win = smem;
@@ -667,7 +663,6 @@ template <int MAXM>
 void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStream_t s) {
     const int64_t lanes = bk.n_slots * kWave;
     if (bk.time_tile > 0 && ckpt == nullptr) {
-        const int32_t win_floats = ((bk.time_tile + bk.hist_len + kSub) + 3) & ~3;
         const int64_t items = (int64_t)((n + bk.time_tile - 1) / bk.time_tile) * bk.n_det *
                               bk.n_slices;
         const int grid = (int)std::min<int64_t>(bk.scan_waves, items);
@@ -675,7 +670,7 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            scan_persistent_lds_bytes(bk.time_tile, bk.hist_len), s, bk.d_a, bk.d_b,
                            bk.d_delay, bk.d_state, bk.d_slices, bk.d_order, bk.n_slices, bk.n_det,
                            lanes, x, n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk,
-                           bk.time_tile, win_floats, bk.d_queue, bk.d_flags);
+                           bk.time_tile, bk.d_queue, bk.d_flags);
     } else if (bk.balanced) {
         const dim3 grid((unsigned)((bk.balance_waves + kScanWaves - 1) / kScanWaves), bk.n_det);
         hipLaunchKernelGGL(scan_fp32_balanced_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
@@ -686,12 +681,11 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride);
     } else {
         const int32_t tile = bk.scan_tile;
-        const int32_t win_floats = ((tile + bk.hist_len + kSub) + 3) & ~3;
         const dim3 grid((bk.n_slices + kScanWaves - 1) / kScanWaves, bk.n_det);
         hipLaunchKernelGGL(scan_fp32_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
                            scan_fp32_lds_bytes(tile, bk.hist_len), s, bk.d_a, bk.d_b, bk.d_delay,
                            bk.d_state, bk.d_slices, bk.d_slice_order, bk.n_slices, lanes, x, n, bk.d_hist,
-                           bk.hist_len, bk.d_partial, bk.max_chunk, tile, win_floats, ckpt,
+                           bk.hist_len, bk.d_partial, bk.max_chunk, tile, ckpt,
                            bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride);
     }
 }
