@@ -543,19 +543,7 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
         // wait until the previous tile of this (detector, slice) has published its state
         uint32_t *flag = flags + (int64_t)det * n_slices + sidx;
         const uint32_t target = epoch + tau;
-        if (lane == 0) {
-            uint32_t spins = 0;
-            while ((int32_t)(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
-                             target) < 0) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins == kSpinLimit) {
-                    __hip_atomic_fetch_add(&queue->error, 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
-        wait_memory();
+        wait_flag(flag, target, lane, &queue->error);
         float2 *st = state + (int64_t)det * lanes_total;
 #pragma unroll
         for (int j = 0; j < MAXM; ++j) {
