@@ -16,6 +16,7 @@ namespace spiir {
 namespace {
 
 constexpr int kPeakThreads = 256;
+constexpr int kUnroll = 4;
 
 struct Best {
     float p;
@@ -76,18 +77,35 @@ __global__ __launch_bounds__(kPeakThreads) void reduce_peaks_kernel(
         const int lo = w * window;
         const int hi = min(lo + window, n);
         Best b{-1.0f, INT_MAX};
-        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            float vr = 0.0f, vi = 0.0f;
+        // kUnroll samples per thread and pass, their loads issued together; the slices are
+        // added in order for every sample, so the sums do not depend on the unrolling
+        for (int i0 = lo + threadIdx.x; i0 < hi; i0 += kUnroll * blockDim.x) {
+            float vr[kUnroll], vi[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) vr[u] = vi[u] = 0.0f;
             for (int p = 0; p < np; ++p) {
-                const float2 v = src[(int64_t)p * part_stride + i];
-                vr += v.x;
-                vi += v.y;
+                float2 v[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int i = i0 + u * (int)blockDim.x;
+                    v[u] = i < hi ? src[(int64_t)p * part_stride + i] : make_float2(0.0f, 0.0f);
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    vr[u] += v[u].x;
+                    vi[u] += v[u].y;
+                }
             }
-            if (zr != nullptr) zr[i] = make_float2(vr, vi);
-            const float pw = abs2_rn(vr, vi);
-            if (pw > b.p) {  // i increases per thread: first occurrence kept
-                b.p = pw;
-                b.i = i - lo;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                if (i >= hi) break;
+                if (zr != nullptr) zr[i] = make_float2(vr[u], vi[u]);
+                const float pw = abs2_rn(vr[u], vi[u]);
+                if (pw > b.p) {  // i increases per thread: first occurrence kept
+                    b.p = pw;
+                    b.i = i - lo;
+                }
             }
         }
         if (peak != nullptr) {
