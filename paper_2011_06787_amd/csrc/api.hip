@@ -615,8 +615,8 @@ spiir_status spiir_filter_chunk(spiir_bank *h, const float *x, int32_t n, float 
         SPIIR_HIP(hipEventRecord(bk.ev_stop[bk.timed], s));
         ++bk.timed;
     }
-    SPIIR_HIP(spiir::launch_hist_update(bk, x, n, s));
-    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), peak, argmax, s));
+    // slice sums, peaks and the history update in one launch
+    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), peak, argmax, x, s));
     return SPIIR_OK;
 }
 
@@ -779,7 +779,8 @@ spiir_status spiir_forward(spiir_bank *h, const float *x, int32_t n, float *z, f
     bk.last_stream = s;
     SPIIR_TRY(zero_stream_state(bk, s));
     SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, reinterpret_cast<float2 *>(ckpt), s));
-    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), nullptr, nullptr, s));
+    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), nullptr, nullptr,
+                                         nullptr, s));
     return SPIIR_OK;
 }
 

@@ -162,7 +162,7 @@ hipError_t launch_backward(const Bank &bk, const float *x, int32_t n, const floa
 hipError_t launch_set_coeffs(const Bank &bk, const float2 *a, const float2 *b, hipStream_t s);
 hipError_t launch_hist_update(const Bank &bk, const float *x, int32_t n, hipStream_t s);
 hipError_t launch_reduce_peaks(const Bank &bk, int32_t n, float2 *z, float *peak,
-                               int32_t *argmax, hipStream_t s);
+                               int32_t *argmax, const float *x, hipStream_t s);
 hipError_t launch_peaks(const float2 *z, int64_t rows, int32_t n, int32_t window, float *peak,
                         int32_t *argmax, hipStream_t s);
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t s);

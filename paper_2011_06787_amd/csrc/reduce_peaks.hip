@@ -55,13 +55,42 @@ __device__ __forceinline__ Best block_best(Best v, Best *scratch) {
 
 // One block per row (template x detector).  The row's series is the sum of
 // `n_parts` partial series starting at `src` with stride `part_stride`.
+// With `hist` non-NULL the grid has one more workgroup per detector (blockIdx.x ==
+// n_rows_per_det) that moves the detector's input history past the packet x (what
+// hist_update_kernel does), saving a launch after the scan; `hist` and `x` are then
+// both non-NULL.
 __global__ __launch_bounds__(kPeakThreads) void reduce_peaks_kernel(
     const float2 *__restrict__ src_all, const int32_t *__restrict__ tmpl_parts, int32_t parts_per_det,
     int32_t part_stride, int32_t n, int32_t n_rows_per_det, float2 *__restrict__ z,
-    float *__restrict__ peak, int32_t *__restrict__ argmax, int32_t window, int32_t n_win) {
+    float *__restrict__ peak, int32_t *__restrict__ argmax, int32_t window, int32_t n_win,
+    float *__restrict__ hist, int32_t hist_len, const float *__restrict__ x) {
     __shared__ Best scratch[kPeakThreads / kWave];
     const int t = blockIdx.x;
     const int det = blockIdx.y;
+    if (t == n_rows_per_det) {
+        // the history workgroup: every old value is read before any is written
+        constexpr int kPer = (kMaxDelay + kPeakThreads) / kPeakThreads;
+        float *h = hist + (int64_t)det * hist_len;
+        const float *xd = x + (int64_t)det * n;
+        float v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int j = threadIdx.x + k * kPeakThreads;
+            v[k] = 0.0f;
+            if (j < hist_len) {
+                const int pos = n - hist_len + j;
+                v[k] = pos >= 0 ? xd[pos] : h[hist_len + pos];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int j = threadIdx.x + k * kPeakThreads;
+            if (j < hist_len) h[j] = v[k];
+        }
+        return;
+    }
+    if (z == nullptr && peak == nullptr) return;   // only the history was asked for
     int p0, np;
     if (tmpl_parts != nullptr) {
         p0 = tmpl_parts[t];
@@ -207,13 +236,16 @@ __global__ void zero_kernel(float4 *__restrict__ p, int64_t n4) {
 }  // namespace
 
 hipError_t launch_reduce_peaks(const Bank &bk, int32_t n, float2 *z, float *peak, int32_t *argmax,
-                               hipStream_t s) {
-    if (n <= 0 || (z == nullptr && peak == nullptr)) return hipSuccess;
+                               const float *x, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
     const int32_t window = bk.peak_window > 0 ? bk.peak_window : n;
     const int32_t n_win = (n + window - 1) / window;
-    hipLaunchKernelGGL(reduce_peaks_kernel, dim3(bk.n_templates, bk.n_det), dim3(kPeakThreads), 0,
-                       s, bk.d_partial, bk.d_tmpl_slices, bk.n_slices, bk.max_chunk, n,
-                       bk.n_templates, z, peak, argmax, window, n_win);
+    const bool hist = bk.hist_len > 0 && x != nullptr;
+    if (!hist && z == nullptr && peak == nullptr) return hipSuccess;
+    hipLaunchKernelGGL(reduce_peaks_kernel, dim3(bk.n_templates + (hist ? 1 : 0), bk.n_det),
+                       dim3(kPeakThreads), 0, s, bk.d_partial, bk.d_tmpl_slices, bk.n_slices,
+                       bk.max_chunk, n, bk.n_templates, z, peak, argmax, window, n_win,
+                       hist ? bk.d_hist : nullptr, bk.hist_len, x);
     return hipGetLastError();
 }
 
@@ -227,7 +259,8 @@ hipError_t launch_peaks(const float2 *z, int64_t rows, int32_t n, int32_t window
         const int64_t cnt = rows - r0 < max_x ? rows - r0 : max_x;
         hipLaunchKernelGGL(reduce_peaks_kernel, dim3((unsigned)cnt, 1), dim3(kPeakThreads), 0, s,
                            z + r0 * n, nullptr, 0, n, n, (int32_t)cnt, nullptr,
-                           peak + r0 * n_win, argmax + r0 * n_win, window, n_win);
+                           peak + r0 * n_win, argmax + r0 * n_win, window, n_win, nullptr, 0,
+                           nullptr);
     }
     return hipGetLastError();
 }
