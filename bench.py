@@ -546,15 +546,26 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         sub = bank.subset(range(min(args.cpu_templates, T)))
+        cores = oracle.threads()
         t1 = time.perf_counter()
         oracle.filter(sub, x_host)
         dt = time.perf_counter() - t1
         upd = sub.n_filters * D * x_host.shape[1]
+        # one thread on a 1/64 slice of the same work: the per-core rate
+        one = bank.subset(range(max(1, min(args.cpu_templates, T) // 64)))
+        oracle.set_threads(1)
+        t2 = time.perf_counter()
+        oracle.filter(one, x_host)
+        dt1 = time.perf_counter() - t2
+        oracle.set_threads(cores)
         result["cpu_baseline"] = {
-            "value": upd / dt, "unit": "filter-sample updates/s", "cores": oracle.threads(),
+            "value": upd / dt, "unit": "filter-sample updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"FP64 oracle, first {sub.n_templates} templates ({sub.n_filters} filters) "
                       f"of the same bank over the same 64-s stream, {dt:.1f} s wall",
+            "per_core_value": one.n_filters * D * x_host.shape[1] / dt1,
+            "per_core_sample": f"1 thread, first {one.n_templates} templates ({one.n_filters} "
+                               f"filters), {dt1:.1f} s wall",
         }
     sb.close()
     del sb

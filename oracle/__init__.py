@@ -67,6 +67,8 @@ def _load():
         lib.spo_autocorr.argtypes = [_I32, _P, _P, _P, _P, _I32, _P]
         lib.spo_noise_power.restype = ctypes.c_int
         lib.spo_threads.argtypes = []
+        lib.spo_set_threads.argtypes = [_I32]
+        lib.spo_set_threads.restype = None
         lib.spo_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -360,6 +362,11 @@ def coherent(z, index, U, tau, shifts):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().spo_threads())
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads for the oracle's parallel loops from now on."""
+    _load().spo_set_threads(int(n))
 
 
 def rel_err(z_test: np.ndarray, z_ref: np.ndarray) -> np.ndarray:

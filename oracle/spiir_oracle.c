@@ -45,6 +45,17 @@ int spo_threads(void)
 #endif
 }
 
+/* Set the number of threads of the parallel loops (n >= 1). */
+void spo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Filtering: Eq. zk (Section II.B.1) as a sum of parallel first-order       */
 /* complex IIR filters.                                                      */
