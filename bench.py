@@ -178,7 +178,8 @@ def batching_run(args, dev):
     out = {"workload": f"batching: {bank.n_templates} templates, {bank.n_filters} filters "
                        f"(lognormal counts), {D} detectors, {n_packets} packets of {chunk} samples",
            "updates_per_packet": bank.n_filters * D * chunk}
-    best_opts, best_mode = dict(filters_per_lane=4, time_tile=0), spiir.MODE_FP32_SCAN
+    # without the autotuner: the configuration it picks on this workload
+    best_opts, best_mode = dict(filters_per_lane=8, time_tile=512), spiir.MODE_FP32_SCAN
     if not args.no_tune:
         t0 = time.perf_counter()
         best, trials = tune.autotune(bank, packets[:8], reps=8)
