@@ -16,6 +16,7 @@ constexpr int kSub = 16;           // samples per register sub-tile of the FP32 
 constexpr int kScanWaves = 4;      // waves per workgroup of the FP32 scan
 constexpr int kMaxDelay = 8191;    // largest supported delay (samples)
 constexpr int kWindowFloats = 12288;  // LDS input window of the FP32 scan (floats)
+constexpr int kSimdKeys = 1 << 15;  // hardware SIMD ids (HW_ID bits 4..15, XCC id)
 constexpr int kLdsPerCu = 160 * 1024;  // LDS of one compute unit (bytes)
 
 // Device bookkeeping of the persistent FP32 scan (one per bank).
@@ -112,6 +113,7 @@ struct Bank {
     int32_t *d_seg_off = nullptr;      // [balance_waves+1]: list of wave w is [off[w], off[w+1])
     uint32_t *d_split_flags = nullptr; // [D][n_splits]: launches whose first part has published
     ScanQueue *d_bqueue = nullptr;     // balanced schedule: launch epoch, finished waves, timeouts
+    uint32_t *d_simd_tab = nullptr;    // balanced schedule: per-SIMD progress of co-resident waves
     float2 *d_bwd_part = nullptr;      // adjoint per-segment sums [D][bwd_max_seg][6][lanes]
     std::vector<int32_t> h_slice_slots;  // slots of every slice (host copy, for planning)
     int32_t *d_order = nullptr;  // [D*n_slices]: det*n_slices + slice, largest slices first

@@ -342,6 +342,77 @@ __device__ __forceinline__ void wait_flag(const uint32_t *flag, uint32_t target,
     wait_memory();
 }
 
+// Issue priority among the waves of the balanced schedule that share a SIMD.  They
+// carry equal planned work, but the SIMD's arbiter favours the older wave, which
+// then finishes long before its younger neighbour (about a quarter of the launch
+// on the realistic bank), and the SIMD runs one wave for the rest of the launch.
+// Each wave therefore publishes its progress (planned cost of the sub-tiles done)
+// in a per-SIMD table every kPeerPeriod sub-tiles and sets its priority to the
+// number of co-resident waves that are ahead of it, so the wave that lags is served
+// first.  The table lives in global memory but only waves of one compute unit
+// share an entry, so workgroup-scope accesses suffice; a stale read only delays a
+// priority change.  Entry (4 words per SIMD): progress of arrival slots 0..2, then
+// the number of waves registered.  A wave past the third on a SIMD stays at the
+// default priority.
+constexpr uint32_t kPeerPeriod = 8;
+
+struct SimdPeers {
+    uint32_t *tab;
+    uint32_t slot;
+    uint32_t done;
+    uint32_t tick;
+    uint32_t seen[3];   // lane 0: the table as read at the previous exchange
+};
+
+__device__ __forceinline__ uint32_t simd_key() {
+    // HW_ID bits 4..15: SIMD, pipe, CU, shader array and engine; XCC_ID: the XCD
+    const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);
+    return ((hw >> 4) & 0xFFFu) | ((xcc & 7u) << 12);
+}
+
+__device__ __forceinline__ SimdPeers simd_join(uint32_t *table, int lane) {
+    SimdPeers p{table + (size_t)simd_key() * 4, 0u, 0u, 0u, {0u, 0u, 0u}};
+    uint32_t slot = 0;
+    if (lane == 0)
+        slot = __hip_atomic_fetch_add(p.tab + 3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    p.slot = __builtin_amdgcn_readfirstlane(slot);
+    return p;
+}
+
+__device__ __forceinline__ void set_priority(uint32_t level) {
+    if (level == 0) __builtin_amdgcn_s_setprio(0);
+    else if (level == 1) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(2);
+}
+
+// After a sub-tile of planned cost `cost`; every kPeerPeriod sub-tiles: compare with
+// the table read at the previous exchange (its loads have long returned), set the
+// priority, publish the progress and read the table again.
+__device__ __forceinline__ void simd_step(SimdPeers &p, uint32_t cost, int lane) {
+    if (p.slot >= 3) return;
+    p.done += cost;
+    if (++p.tick % kPeerPeriod != 0) return;
+    uint32_t ahead = 0;
+    if (lane == 0) ahead = (p.seen[0] > p.done) + (p.seen[1] > p.done) + (p.seen[2] > p.done);
+    set_priority(__builtin_amdgcn_readfirstlane(ahead));
+    if (lane == 0) {
+        __hip_atomic_store(p.tab + p.slot, p.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            p.seen[k] = __hip_atomic_load(p.tab + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+__device__ __forceinline__ void simd_leave(SimdPeers &p, int lane) {
+    __builtin_amdgcn_s_setprio(0);
+    if (lane == 0) {
+        if (p.slot < 3)
+            __hip_atomic_store(p.tab + p.slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_sub(p.tab + 3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
 // First sample of the sub-tile that starts at fraction phi of a packet of n samples.
 __device__ __forceinline__ int phi_sample(int32_t phi, int32_t n) {
     if (phi >= kPhiOne) return n;
@@ -366,7 +437,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
     int32_t n_splits, uint32_t *__restrict__ flags, ScanQueue *__restrict__ queue,
     int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
     int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, float2 *__restrict__ ckpt,
-    int32_t ckpt_stride, int32_t n_seg) {
+    int32_t ckpt_stride, int32_t n_seg, uint32_t *__restrict__ simd_tab) {
     extern __shared__ float smem[];
     float *win = smem;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -379,6 +450,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
     const float *hd = hist + (int64_t)det * hist_len;
     load_window(win, xd, hd, hist_len, 0, n, threadIdx.x, blockDim.x);
     __syncthreads();
+    SimdPeers peers = simd_join(simd_tab, lane);
     float2 *st = state + (int64_t)det * lanes_total;
     float2 *ck = ckpt != nullptr ? ckpt + (int64_t)det * n_seg * lanes_total : nullptr;
     uint32_t *fl = flags + (int64_t)det * n_splits;
@@ -411,7 +483,10 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
                 base[j] = 0;
             }
         }
-        if (sg.phi0 > 0) wait_flag(fl + sg.flag, epoch + 1u, lane, &queue->error);
+        if (sg.phi0 > 0) {
+            __builtin_amdgcn_s_setprio(0);   // a waiting wave yields the SIMD
+            wait_flag(fl + sg.flag, epoch + 1u, lane, &queue->error);
+        }
 #pragma unroll
         for (int j = 0; j < MAXM; ++j) {
             if (j < m) {
@@ -432,6 +507,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
         for (int s0 = t0; s0 < full_end; s0 += kSub) {
             sub_tile<MAXM, false>(win, red_sample, lane, m, s0, kSub, ar, ai, br, bi, base, yr,
                                   yi, pout + s0);
+            simd_step(peers, 20u * (uint32_t)m + 9u, lane);
             const int eo = s0 + kSub;
             if (ck != nullptr && eo % ckpt_stride == 0 && eo < n) {
                 float2 *cs = ck + (int64_t)(eo / ckpt_stride) * lanes_total;
@@ -460,6 +536,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
                 if (j < m) st[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
         }
     }
+    simd_leave(peers, lane);
     // the last wave to finish advances the epoch for the next launch
     if (lane == 0) {
         const uint32_t total = gridDim.x * gridDim.y * kScanWaves;
@@ -666,7 +743,8 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            bk.d_state, bk.d_slices, bk.n_slices, bk.d_segs, bk.d_seg_off,
                            bk.balance_waves, bk.n_splits, bk.d_split_flags, bk.d_bqueue, lanes, x,
                            n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk, ckpt,
-                           bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride);
+                           bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride,
+                           bk.d_simd_tab);
     } else {
         const int32_t tile = bk.scan_tile;
         const dim3 grid((bk.n_slices + kScanWaves - 1) / kScanWaves, bk.n_det);
