@@ -270,7 +270,7 @@ spiir_status plan_balanced(spiir::Bank &bk, hipStream_t s) {
     SPIIR_TRY(dev_alloc(bk, &bk.d_seg_off, W + 1));
     SPIIR_TRY(dev_alloc(bk, &bk.d_split_flags, std::max<int64_t>((int64_t)bk.n_det * splits, 4)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_bqueue, 1));
-    SPIIR_TRY(dev_alloc(bk, &bk.d_simd_tab, (int64_t)spiir::kSimdKeys * 4));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_simd_tab, (int64_t)spiir::kSimdKeys * spiir::kPeerTableWords));
     SPIIR_TRY(upload(bk.d_segs, segs, s));
     SPIIR_TRY(upload(bk.d_seg_off, off, s));
     SPIIR_HIP(hipStreamSynchronize(s));   // the host vectors die at return
@@ -300,7 +300,8 @@ spiir_status zero_queue(spiir::Bank &bk, hipStream_t s) {
     if (bk.balanced) {
         SPIIR_HIP(spiir::launch_zero(bk.d_bqueue, round16(sizeof(spiir::ScanQueue)), s));
         SPIIR_HIP(spiir::launch_zero(bk.d_simd_tab,
-                                     round16((int64_t)spiir::kSimdKeys * 4 * (int64_t)sizeof(uint32_t)),
+                                     round16((int64_t)spiir::kSimdKeys * spiir::kPeerTableWords *
+                                             (int64_t)sizeof(uint32_t)),
                                      s));
         SPIIR_HIP(spiir::launch_zero(bk.d_split_flags,
                                      round16(std::max<int64_t>((int64_t)bk.n_det * bk.n_splits, 4) *

@@ -17,6 +17,7 @@ constexpr int kScanWaves = 4;      // waves per workgroup of the FP32 scan
 constexpr int kMaxDelay = 8191;    // largest supported delay (samples)
 constexpr int kWindowFloats = 12288;  // LDS input window of the FP32 scan (floats)
 constexpr int kSimdKeys = 1 << 15;  // hardware SIMD ids (HW_ID bits 4..15, XCC id)
+constexpr int kPeerTableWords = 8;  // words per SIMD of the balanced scan's progress table
 constexpr int kLdsPerCu = 160 * 1024;  // LDS of one compute unit (bytes)
 
 // Device bookkeeping of the persistent FP32 scan (one per bank).

@@ -351,17 +351,19 @@ __device__ __forceinline__ void wait_flag(const uint32_t *flag, uint32_t target,
 // number of co-resident waves that are ahead of it, so the wave that lags is served
 // first.  The table lives in global memory but only waves of one compute unit
 // share an entry, so workgroup-scope accesses suffice; a stale read only delays a
-// priority change.  Entry (4 words per SIMD): progress of arrival slots 0..2, then
-// the number of waves registered.  A wave past the third on a SIMD stays at the
-// default priority.
+// priority change.  Entry (kPeerWords words per SIMD): progress of arrival slots
+// 0..kPeerSlots-1, then the number of waves registered.  A wave past the last slot
+// stays at the default priority.
 constexpr uint32_t kPeerPeriod = 8;
+constexpr uint32_t kPeerSlots = 4;
+constexpr uint32_t kPeerWords = kPeerTableWords;
 
 struct SimdPeers {
     uint32_t *tab;
     uint32_t slot;
     uint32_t done;
     uint32_t tick;
-    uint32_t seen[3];   // lane 0: the table as read at the previous exchange
+    uint32_t seen[kPeerSlots];   // lane 0: the table as read at the previous exchange
 };
 
 __device__ __forceinline__ uint32_t simd_key() {
@@ -372,10 +374,11 @@ __device__ __forceinline__ uint32_t simd_key() {
 }
 
 __device__ __forceinline__ SimdPeers simd_join(uint32_t *table, int lane) {
-    SimdPeers p{table + (size_t)simd_key() * 4, 0u, 0u, 0u, {0u, 0u, 0u}};
+    SimdPeers p{table + (size_t)simd_key() * kPeerWords, 0u, 0u, 0u, {}};
     uint32_t slot = 0;
     if (lane == 0)
-        slot = __hip_atomic_fetch_add(p.tab + 3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        slot = __hip_atomic_fetch_add(p.tab + kPeerSlots, 1u, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
     p.slot = __builtin_amdgcn_readfirstlane(slot);
     return p;
 }
@@ -383,23 +386,27 @@ __device__ __forceinline__ SimdPeers simd_join(uint32_t *table, int lane) {
 __device__ __forceinline__ void set_priority(uint32_t level) {
     if (level == 0) __builtin_amdgcn_s_setprio(0);
     else if (level == 1) __builtin_amdgcn_s_setprio(1);
-    else __builtin_amdgcn_s_setprio(2);
+    else if (level == 2) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(3);
 }
 
 // After a sub-tile of planned cost `cost`; every kPeerPeriod sub-tiles: compare with
 // the table read at the previous exchange (its loads have long returned), set the
 // priority, publish the progress and read the table again.
 __device__ __forceinline__ void simd_step(SimdPeers &p, uint32_t cost, int lane) {
-    if (p.slot >= 3) return;
+    if (p.slot >= kPeerSlots) return;
     p.done += cost;
     if (++p.tick % kPeerPeriod != 0) return;
     uint32_t ahead = 0;
-    if (lane == 0) ahead = (p.seen[0] > p.done) + (p.seen[1] > p.done) + (p.seen[2] > p.done);
+    if (lane == 0) {
+#pragma unroll
+        for (uint32_t k = 0; k < kPeerSlots; ++k) ahead += p.seen[k] > p.done;
+    }
     set_priority(__builtin_amdgcn_readfirstlane(ahead));
     if (lane == 0) {
         __hip_atomic_store(p.tab + p.slot, p.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (uint32_t k = 0; k < kPeerSlots; ++k)
             p.seen[k] = __hip_atomic_load(p.tab + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
@@ -407,9 +414,10 @@ __device__ __forceinline__ void simd_step(SimdPeers &p, uint32_t cost, int lane)
 __device__ __forceinline__ void simd_leave(SimdPeers &p, int lane) {
     __builtin_amdgcn_s_setprio(0);
     if (lane == 0) {
-        if (p.slot < 3)
+        if (p.slot < kPeerSlots)
             __hip_atomic_store(p.tab + p.slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_fetch_sub(p.tab + 3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_sub(p.tab + kPeerSlots, 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
