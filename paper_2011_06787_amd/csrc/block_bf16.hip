@@ -303,26 +303,93 @@ __global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
     }
 }
 
-// Output product, one workgroup of (2L/64) waves per (template, 128 columns); a
-// column is (detector, block).  Wave w computes output rows [64w, 64w+64) x the
-// 128 columns: 2 x 4 accumulator tiles of 32x32.  Per K step of 16 the B operand
-// (128 columns x 16 entries, hi and lo) is staged once into LDS for all waves
-// (double-buffered; 48-byte column pitch so the 16-byte fragment reads of 16
-// lanes cover the 64 banks once), while each wave streams its own A fragments
-// from global memory, prefetching the next step's during the current MFMAs.
+// Output product, one workgroup of RW x CH waves per (template, CH x 128 columns),
+// RW = 2L/64; a column is (detector, block).  Wave (r, h) computes output rows
+// [64r, 64r+64) x columns [128h, 128h+128) of the tile: 2 x 4 accumulator tiles of
+// 32x32.  Per K step of 16 both operands are copied into LDS by direct
+// global-to-LDS loads (each lane's 16 bytes land at the instruction's LDS base + 16
+// x lane), shared by the waves that need them: the B operand (CH x 128 columns x 16
+// entries, hi and lo: CH x 8 KB) and the A rows (RW x 2 row tiles, hi and lo: RW x
+// 4 KB); every A byte serves CH x 128 columns.  The loads run three steps ahead in
+// a ring of kStages buffers: with fewer steps of matrix-core work in front of them,
+// their latency (the block states come from HBM) set the kernel's time.  The fragments are read from LDS with
+// explicit waits: the compiler, which cannot tell the ring's stages apart, would
+// otherwise wait for every load in flight before each read.
+// LDS layout of a stage: A [row tile][plane][32 rows x 16 k] as in global memory,
+// then B [plane][column][k half] x 16 bytes; either way the fragment reads of a
+// wave cover 1 KB contiguously, without bank conflicts.
 // Workgroups are dispatched round-robin over the XCDs (id % kXcds); the mapping
 // gives every column tile of a template to the same XCD, one after the other, so
 // the template's operand is fetched into that XCD's L2 once.
 constexpr int kXcds = 8;
-constexpr int kOutCols = 128;
-constexpr int kBPitch = 24;   // bf16 per staged column per plane (16 used + 8 pad)
+constexpr int kOutCols = 128;   // columns per wave
+constexpr int kStages = 4;
+constexpr int kALoads = 4;      // 1-KB direct loads of A per row wave per stage
 
-__global__ __launch_bounds__(512) void block_output_kernel(
+// column waves per workgroup for RW row waves (at most 8 waves per workgroup)
+__host__ __device__ constexpr int out_col_waves(int rw) { return rw <= 4 ? 2 : 1; }
+
+__host__ __device__ constexpr int out_stage_elems(int rw) {
+    return 2 * rw * 1024 + 2 * 2 * out_col_waves(rw) * kOutCols * 8;
+}
+
+size_t block_output_lds_bytes(int rw) { return (size_t)kStages * out_stage_elems(rw) * sizeof(uint16_t); }
+
+// s_waitcnt with vmcnt = N and lgkmcnt = 0 (gfx9 encoding: vmcnt in bits 3:0 and
+// 15:14, expcnt 6:4 left at its maximum, lgkmcnt 11:8)
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+// 16-byte LDS read at byte address `addr` (+ imm); the result is tied to an
+// explicit lgkmcnt wait by the caller
+template <int OFF>
+__device__ __forceinline__ bf16x8 lds_read16(uint32_t addr) {
+    bf16x8 v;
+    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
+    return v;
+}
+
+// LDS (address space 3) pointer to element `elem` of `smem`, and its byte address
+__device__ __forceinline__ __attribute__((address_space(3))) void *lds_elem(uint16_t *smem, int elem) {
+    return (__attribute__((address_space(3))) void *)(
+        (__attribute__((address_space(3))) uint16_t *)smem + elem);
+}
+
+// direct global-to-LDS load of 16 bytes per lane: lane i's bytes from `src` land at
+// element `elem` of `smem` (wave-uniform) + 16 x i bytes
+__device__ __forceinline__ void lds_dma16(const void *src, uint16_t *smem, int elem) {
+    __builtin_amdgcn_global_load_lds(src, lds_elem(smem, elem), 16, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t lds_byte_addr(uint16_t *smem) {
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint16_t *)smem;
+}
+
+// lgkmcnt wait that the MFMAs reading a and b cannot be moved above
+template <int N>
+__device__ __forceinline__ void wait_lgkm(bf16x8 &a, bf16x8 &b) {
+    asm volatile("s_waitcnt lgkmcnt(%2)" : "+v"(a), "+v"(b) : "i"(N));
+}
+
+template <int RW>
+__global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_kernel(
     const BTemplate *__restrict__ tmpls, const uint16_t *__restrict__ pa,
     const uint16_t *__restrict__ yt, int64_t y_per_det, const uint16_t *__restrict__ xs,
     int64_t xs_stride, int32_t hist_pad, int32_t n_det, int32_t L, int32_t nb, int32_t n,
     int32_t n_templates, float *__restrict__ z, int32_t n_col_tiles) {
-    __shared__ __attribute__((aligned(16))) uint16_t bs[2][2][kOutCols * kBPitch];
+    constexpr int CH = out_col_waves(RW);
+    constexpr int kWaves = RW * CH;
+    constexpr int kCols = CH * kOutCols;                // columns of the workgroup's tile
+    constexpr int kBLoadsWg = 2 * 2 * kCols / kWave;    // 1-KB direct loads of B per stage
+    constexpr int kALoadsWg = kALoads * RW;             // and of A
+    static_assert(kBLoadsWg % kWaves == 0 && kALoadsWg % kWaves == 0,
+                  "every wave issues the same number of loads");
+    constexpr int kMyLoads = (kBLoadsWg + kALoadsWg) / kWaves;   // per wave per stage
+    constexpr int kStageElems = out_stage_elems(RW);
+    extern __shared__ __attribute__((aligned(16))) uint16_t smem_out[];
     const int wg = blockIdx.x;
     const int xcd = wg % kXcds;
     const int seq = wg / kXcds;
@@ -330,19 +397,19 @@ __global__ __launch_bounds__(512) void block_output_kernel(
     const int col_tile = seq % n_col_tiles;
     if (t >= n_templates) return;
     const BTemplate bt = tmpls[t];
-    const int nthreads = blockDim.x;
-    const int tid = threadIdx.x;
-    const int wave = tid / kWave;
-    const int lane = tid % kWave;
-    const int rt_per = (2 * L) / 32;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    const int rw = wave % RW, ch = wave / RW;   // row wave, column wave
+    const int rt_per = 2 * RW;
     const int kg = (lane / 32) * 8;
     const int ncols = n_det * nb;
     const int64_t row_len = 2 * (int64_t)bt.fpad;
     const int nks = bt.nks_p + bt.nks_m;
+    const uint32_t ring = lds_byte_addr(smem_out);
 
-    // global source of the staged B entries of step ks for column c (8 entries, one plane)
+    // global source of the B entries of step ks for column c (8 entries of one plane)
     auto b_src = [&](int ks, int c, int plane, int half) -> const uint16_t * {
-        const int cc = min(col_tile * kOutCols + c, ncols - 1);
+        const int cc = min(col_tile * kCols + c, ncols - 1);
         const int det = cc / nb, blk = cc % nb;
         if (ks < bt.nks_p)
             return yt + (int64_t)plane * n_det * y_per_det + (int64_t)det * y_per_det + bt.y_off +
@@ -350,34 +417,26 @@ __global__ __launch_bounds__(512) void block_output_kernel(
         return xs + (int64_t)plane * n_det * xs_stride + (int64_t)det * xs_stride + hist_pad +
                (int64_t)blk * L + bt.sigma_lo + 16 * (ks - bt.nks_p) + 8 * half;
     };
-    // (column, plane, half) 16-byte items per step; a thread owns at most kBItems of them
-    // (128 threads at L = 64 for 512 items).  The global loads of the next step are issued
-    // before the current step's products and written to LDS after them, so their latency
-    // hides behind the matrix-core work.
-    constexpr int kBItems = 4;
-    const int n_b_items = kOutCols * 2 * 2;
-    auto stage_load = [&](int ks, bf16x8 (&v)[kBItems]) {
+    // this wave's share of the direct loads of step ks into stage ks % kStages: A
+    // loads q = wave, wave + kWaves, ... (1 KB each, the step's A rows being
+    // contiguous), B loads likewise, each covering items 64q..64q+63 with item
+    // e = (plane * kCols + column) * 2 + half: the two halves of a column's 32
+    // contiguous bytes go to neighbouring lanes, one cache-line request for both
+    auto issue = [&](int ks) {
+        const int st = (ks % kStages) * kStageElems;
+        const uint16_t *asrc = pa + bt.a_off + (int64_t)ks * rt_per * 1024 + lane * 8;
 #pragma unroll
-        for (int i = 0; i < kBItems; ++i) {
-            const int e = tid + i * nthreads;
-            if (e < n_b_items) {
-                const int c = e >> 2, plane = (e >> 1) & 1, half = e & 1;
-                v[i] = load8(b_src(ks, c, plane, half));
-            }
+        for (int i = 0; i < kALoadsWg / kWaves; ++i) {
+            const int q = wave + i * kWaves;
+            lds_dma16(asrc + q * 512, smem_out, st + q * 512);
         }
-    };
-    auto stage_store = [&](int buf, const bf16x8 (&v)[kBItems]) {
 #pragma unroll
-        for (int i = 0; i < kBItems; ++i) {
-            const int e = tid + i * nthreads;
-            if (e < n_b_items) {
-                const int c = e >> 2, plane = (e >> 1) & 1, half = e & 1;
-                *reinterpret_cast<bf16x8 *>(&bs[buf][plane][c * kBPitch + 8 * half]) = v[i];
-            }
+        for (int i = 0; i < kBLoadsWg / kWaves; ++i) {
+            const int q = wave + i * kWaves;
+            const int e = q * kWave + lane;
+            const int c = (e >> 1) % kCols, plane = (e >> 1) / kCols;
+            lds_dma16(b_src(ks, c, plane, e & 1), smem_out, st + 2 * RW * 1024 + q * kWave * 8);
         }
-    };
-    auto a_ptr = [&](int ks, int r) -> const uint16_t * {
-        return pa + bt.a_off + ((int64_t)ks * rt_per + 2 * wave + r) * 1024 + (lane % 32) * 16 + kg;
     };
 
     f32x16 acc[2][4];
@@ -386,53 +445,56 @@ __global__ __launch_bounds__(512) void block_output_kernel(
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f32x16{};
 
-    bf16x8 ah[2], al[2];
-    if (nks > 0) {
-        bf16x8 v0[kBItems];
-        stage_load(0, v0);
-        stage_store(0, v0);
+    // byte offsets of this lane's fragments within a stage
+    const uint32_t a_frag = (uint32_t)((2 * rw * 1024 + (lane % 32) * 16 + kg) * 2);
+    const uint32_t b_frag =
+        (uint32_t)((2 * RW * 1024 + ((ch * kOutCols + (lane % 32)) * 2 + kg / 8) * 8) * 2);
+    constexpr int kPl = 2 * kCols * 8 * 2;   // bytes from plane 0 to plane 1 of B
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            ah[r] = load8(a_ptr(0, r));
-            al[r] = load8(a_ptr(0, r) + 512);
-        }
-    }
-    __syncthreads();
+    for (int i = 0; i < kStages - 1; ++i)
+        if (i < nks) issue(i);
     for (int ks = 0; ks < nks; ++ks) {
-        const int buf = ks & 1;
-        // prefetch the next step: A into registers, B into the other LDS buffer
-        bf16x8 nh[2], nl[2], nb[kBItems];
-        const bool more = ks + 1 < nks;
-        if (more) {
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                nh[r] = load8(a_ptr(ks + 1, r));
-                nl[r] = load8(a_ptr(ks + 1, r) + 512);
-            }
-            stage_load(ks + 1, nb);
-        }
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            const int c = ct * 32 + (lane % 32);
-            const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(&bs[buf][0][c * kBPitch + kg]);
-            const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&bs[buf][1][c * kBPitch + kg]);
-#pragma unroll
-            for (int r = 0; r < 2; ++r) acc[r][ct] = mma3(ah[r], al[r], bh, bl, acc[r][ct]);
-        }
-        if (more) {
-            stage_store(buf ^ 1, nb);
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                ah[r] = nh[r];
-                al[r] = nl[r];
-            }
-        }
-        __syncthreads();   // buffer `buf` free, buffer `buf^1` complete
+        // this step's operands have landed once at most the later steps' loads are in
+        // flight; after the barrier every wave's part is visible, and the stage read
+        // in the previous step (every wave is past its reads) is free for step
+        // ks + kStages - 1
+        static_assert(kStages == 4, "the waits below assume two later steps in flight");
+        const int later = min(nks - 1 - ks, kStages - 2);
+        if (later >= 2) wait_vm_lgkm0<2 * kMyLoads>();
+        else if (later == 1) wait_vm_lgkm0<kMyLoads>();
+        else wait_vm_lgkm0<0>();
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        if (ks + kStages - 1 < nks) issue(ks + kStages - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t base = ring + (uint32_t)((ks % kStages) * kStageElems * 2);
+        const uint32_t pa_ = base + a_frag, pb = base + b_frag;
+        bf16x8 ah0 = lds_read16<0>(pa_), al0 = lds_read16<1024>(pa_);
+        bf16x8 ah1 = lds_read16<2048>(pa_), al1 = lds_read16<3072>(pa_);
+        // B: plane 1 kPl bytes after plane 0; accumulator column tile ct at +32 x 32 x ct
+        bf16x8 bh0 = lds_read16<0>(pb), bl0 = lds_read16<kPl>(pb);
+        bf16x8 bh1 = lds_read16<1024>(pb), bl1 = lds_read16<kPl + 1024>(pb);
+        bf16x8 bh2 = lds_read16<2048>(pb), bl2 = lds_read16<kPl + 2048>(pb);
+        bf16x8 bh3 = lds_read16<3072>(pb), bl3 = lds_read16<kPl + 3072>(pb);
+        wait_lgkm<6>(ah0, al0);
+        wait_lgkm<6>(ah1, al1);
+        wait_lgkm<6>(bh0, bl0);
+        acc[0][0] = mma3(ah0, al0, bh0, bl0, acc[0][0]);
+        acc[1][0] = mma3(ah1, al1, bh0, bl0, acc[1][0]);
+        wait_lgkm<4>(bh1, bl1);
+        acc[0][1] = mma3(ah0, al0, bh1, bl1, acc[0][1]);
+        acc[1][1] = mma3(ah1, al1, bh1, bl1, acc[1][1]);
+        wait_lgkm<2>(bh2, bl2);
+        acc[0][2] = mma3(ah0, al0, bh2, bl2, acc[0][2]);
+        acc[1][2] = mma3(ah1, al1, bh2, bl2, acc[1][2]);
+        wait_lgkm<0>(bh3, bl3);
+        acc[0][3] = mma3(ah0, al0, bh3, bl3, acc[0][3]);
+        acc[1][3] = mma3(ah1, al1, bh3, bl3, acc[1][3]);
     }
     // rows (2j + re/im): accumulator entries 4q..4q+3 are (j0 re, j0 im, j0+1 re, j0+1 im)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
-        const int c = col_tile * kOutCols + ct * 32 + (lane % 32);
+        const int c = col_tile * kCols + ch * kOutCols + ct * 32 + (lane % 32);
         if (c >= ncols) continue;
         const int det = c / nb, blk = c % nb;
         float *zr = z + 2 * (((int64_t)det * n_templates + t) * n + (int64_t)blk * L);
@@ -440,7 +502,7 @@ __global__ __launch_bounds__(512) void block_output_kernel(
         for (int r = 0; r < 2; ++r) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = 64 * wave + 32 * r + 8 * q + 4 * (lane / 32);
+                const int row = 64 * rw + 32 * r + 8 * q + 4 * (lane / 32);
                 const int j0 = row / 2;
                 const float4 v = make_float4(acc[r][ct][4 * q], acc[r][ct][4 * q + 1],
                                              acc[r][ct][4 * q + 2], acc[r][ct][4 * q + 3]);
@@ -467,9 +529,19 @@ size_t block_state_lds_bytes(const Bank &bk) {
 }
 
 hipError_t prepare_block_bf16(const Bank &bk) {
-    return hipFuncSetAttribute((const void *)block_state_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)block_state_lds_bytes(bk));
+    hipError_t e = hipFuncSetAttribute((const void *)block_state_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)block_state_lds_bytes(bk));
+    if (e != hipSuccess) return e;
+    const void *out[3] = {(const void *)block_output_kernel<2>, (const void *)block_output_kernel<4>,
+                          (const void *)block_output_kernel<8>};
+    const int rw[3] = {2, 4, 8};
+    for (int k = 0; k < 3; ++k) {
+        e = hipFuncSetAttribute(out[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)block_output_lds_bytes(rw[k]));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *z, hipStream_t s) {
@@ -492,12 +564,22 @@ hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *
                            bk.d_yt, bk.y_per_det, xwin);
     }
     const int ncols = bk.n_det * nb;
-    const int col_tiles = (ncols + kOutCols - 1) / kOutCols;
     const int64_t groups = (bk.n_templates + kXcds - 1) / kXcds;
-    const dim3 grid((unsigned)(groups * kXcds * col_tiles));
-    hipLaunchKernelGGL(block_output_kernel, grid, dim3((2 * L / 64) * kWave), 0, s, bk.d_btmpl,
-                       bk.d_pa, bk.d_yt, bk.y_per_det, bk.d_xs, bk.xs_stride, bk.hist_pad, bk.n_det,
-                       L, nb, n, bk.n_templates, reinterpret_cast<float *>(z), col_tiles);
+#define SPIIR_BLOCK_OUT(RW)                                                                   \
+    const int col_tiles = (ncols + out_col_waves(RW) * kOutCols - 1) / (out_col_waves(RW) * kOutCols); \
+    const dim3 grid((unsigned)(groups * kXcds * col_tiles));                                  \
+    hipLaunchKernelGGL(block_output_kernel<RW>, grid, dim3(RW * out_col_waves(RW) * kWave),      \
+                       block_output_lds_bytes(RW), s, bk.d_btmpl,                                \
+                       bk.d_pa, bk.d_yt, bk.y_per_det, bk.d_xs, bk.xs_stride, bk.hist_pad,       \
+                       bk.n_det, L, nb, n, bk.n_templates, reinterpret_cast<float *>(z),         \
+                       col_tiles)
+    switch (2 * L / 64) {
+    case 2: { SPIIR_BLOCK_OUT(2); break; }
+    case 4: { SPIIR_BLOCK_OUT(4); break; }
+    case 8: { SPIIR_BLOCK_OUT(8); break; }
+    default: return hipErrorInvalidValue;
+    }
+#undef SPIIR_BLOCK_OUT
     return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ def test_chunk_sizes_agree_with_oracle(gpu, chunk, time_tile, balance_wgs):
 
 
 @pytest.mark.parametrize("time_tile, balance_wgs", [(16, 0), (256, 0), (4096, 0), (-1, 0),
-                                                  (0, 1), (-1, 2), (0, 8)])
+                                                  (0, 1), (-1, 2), (0, 4), (0, 8)])
 def test_schedules_on_a_larger_bank(gpu, time_tile, balance_wgs):
     # many slices and tiles: the persistent queue's dependency chains, and the slice
     # queue with few and with many resident workgroups per compute unit
@@ -208,13 +208,14 @@ def test_standalone_peaks_bit_exact(gpu, rows, n, window):
 
 
 def test_realistic_bank_full_size_sampled(gpu):
-    """The 1024-template realistic bank in 1-s packets (the benchmark's launch
-    configuration), checked on a seeded sample of templates over 8 s, with the
-    first and last templates always included."""
+    """The 1024-template realistic bank in 1-s packets in the benchmark's launch
+    configuration (default filters per lane, balanced schedule with 2 workgroups per
+    compute unit), checked on a seeded sample of templates over 8 s, with the first
+    and last templates always included."""
     w = synth.realistic()
     n = 8 * 2048
     x = w.input()[:, :n]
-    z, pk, am = run_stream(gpu, w.bank, x, 2048)
+    z, pk, am = run_stream(gpu, w.bank, x, 2048, balance_wgs=2)
     pick = sorted(set([0, w.bank.n_templates - 1]) |
                   set(np.random.default_rng(9).choice(w.bank.n_templates, 14, replace=False).tolist()))
     sub = w.bank.subset(pick)
