@@ -179,7 +179,7 @@ def batching_run(args, dev):
                        f"(lognormal counts), {D} detectors, {n_packets} packets of {chunk} samples",
            "updates_per_packet": bank.n_filters * D * chunk}
     # without the autotuner: the configuration it picks on this workload
-    best_opts, best_mode = dict(filters_per_lane=8, time_tile=512), spiir.MODE_FP32_SCAN
+    best_opts, best_mode = dict(filters_per_lane=8, time_tile=0, balance_wgs=3), spiir.MODE_FP32_SCAN
     if not args.no_tune:
         t0 = time.perf_counter()
         best, trials = tune.autotune(bank, packets[:8], reps=8)
