@@ -79,7 +79,8 @@ def parse():
                    help="skip the batching workload (16384 templates, 3 detectors, 0.25-s packets)")
     p.add_argument("--batching-only", action="store_true")
     p.add_argument("--batching-packets", type=int, default=240)
-    p.add_argument("--no-tune", action="store_true", help="batching: skip the autotuner")
+    p.add_argument("--no-tune", action="store_true",
+                   help="skip the autotuners (batching schedule, precision FP32 schedule)")
     p.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
     p.add_argument("--diff-only", action="store_true")
     p.add_argument("--diff-filters-per-lane", type=int, default=4,
@@ -106,10 +107,18 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 4}), flush=True)
 
 
+# FP32 scan schedules tried on the precision workload (3 x 65,536 samples: the packet does not
+# fit one LDS window, so the balanced schedule is not available)
+PRECISION_SCAN = [dict(filters_per_lane=4, time_tile=0)] + \
+    [dict(filters_per_lane=f, time_tile=t) for f in (4, 8) for t in (512, 1024, 2048)]
+
+
 def precision_comparison(args, dev):
     """Split-bf16 block form vs FP32 scan on the precision workload: the 1024-template
     bank over 3 detector streams of 32 s, one packet per stream; relative SNR error of
-    each against the FP64 oracle on seeded templates."""
+    each against the FP64 oracle on seeded templates.  The FP32 scan runs in the
+    schedule the autotuner picks among PRECISION_SCAN (without the tuner: the one it
+    picks there), so the comparison is against the FP32 path at its best."""
     import torch
     import oracle
     from paper_2011_06787_amd import spiir
@@ -124,7 +133,19 @@ def precision_comparison(args, dev):
     out = {"workload": "precision: 1024 templates x U{200..800} filters (521,135), 3 detector "
                        "streams of 32 s at 2048 Hz, one packet per stream",
            "updates_per_pass": F * D * N}
-    modes = [("fp32_scan", dict(mode=spiir.MODE_FP32_SCAN))]
+    # without the autotuner: the schedule it picks on this workload
+    scan_opts = dict(filters_per_lane=8, time_tile=1024)
+    if not args.no_tune:
+        from paper_2011_06787_amd import tune
+        t_tune = time.perf_counter()
+        best, trials = tune.autotune(bank, [x], scan_candidates=PRECISION_SCAN, block_candidates=[],
+                                     reps=2)
+        scan_opts = dict(best.opts)
+        out["fp32_autotune"] = {"seconds": time.perf_counter() - t_tune, "chosen": scan_opts,
+                                "trials": [{**t.opts, "updates_per_s": t.updates_per_s}
+                                           for t in trials]}
+        log(f"precision fp32 autotune: {scan_opts} {best.updates_per_s:.4g} upd/s")
+    modes = [("fp32_scan", dict(mode=spiir.MODE_FP32_SCAN, **scan_opts))]
     for L in ([args.block_len] if args.block_len else [64, 128, 256]):
         modes.append((f"bf16_block_L{L}", dict(mode=spiir.MODE_BF16_BLOCK, block_len=L)))
     for name, kw in modes:
@@ -157,6 +178,7 @@ def precision_comparison(args, dev):
         torch.cuda.empty_cache()
     best = max((k for k in out if k.startswith("bf16_block")), key=lambda k: out[k]["updates_per_s"])
     out["best_block"] = best
+    out["fp32_scan"]["options"] = scan_opts
     out["block_speedup_vs_fp32"] = out[best]["updates_per_s"] / out["fp32_scan"]["updates_per_s"]
     return out
 
