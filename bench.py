@@ -79,6 +79,9 @@ def parse():
                    help="skip the batching workload (16384 templates, 3 detectors, 0.25-s packets)")
     p.add_argument("--batching-only", action="store_true")
     p.add_argument("--batching-packets", type=int, default=240)
+    p.add_argument("--diff-ckpt-stride", type=int, default=512,
+                   help="differentiation: samples per checkpoint segment (multiple of 128; "
+                        "512 gave the fastest forward + backward on this workload)")
     p.add_argument("--no-tune", action="store_true",
                    help="skip the autotuners (batching schedule, precision FP32 schedule)")
     p.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
@@ -267,7 +270,7 @@ def batching_run(args, dev):
 
 def differentiation_run(args, dev):
     """Differentiation workload: 256 templates x 512 filters driven by an impulse of 8192
-    samples, targets = chirps; forward (with checkpoints every 2048 samples) and the
+    samples, targets = chirps; forward (with checkpoints every --diff-ckpt-stride samples) and the
     reverse-time adjoint, timed with events; gradient of the mean overlap loss checked
     against the oracle's closed form on 16 seeded templates."""
     import torch
@@ -278,7 +281,7 @@ def differentiation_run(args, dev):
     target = synth.chirp_targets(0, bank.n_templates, n)
     x = torch.from_numpy(w.input()).to(dev)
     g = torch.from_numpy(target).to(dev)
-    sb = spiir.SpiirBank.from_bank(bank, max_chunk=n, ckpt_stride=2048,
+    sb = spiir.SpiirBank.from_bank(bank, max_chunk=n, ckpt_stride=args.diff_ckpt_stride,
                                    filters_per_lane=args.diff_filters_per_lane)
     a = torch.from_numpy(bank.a).to(dev)
     b = torch.from_numpy(bank.b).to(dev)
@@ -314,7 +317,7 @@ def differentiation_run(args, dev):
     ga_h, gb_h = ga.cpu().numpy()[idx], gb.cpu().numpy()[idx]
     rel = lambda u, v: float(np.linalg.norm(u - v) / np.linalg.norm(v))
     out = {"workload": "differentiation: 256 templates x 512 filters, impulse input of 8192 samples, "
-                       "chirp targets, checkpoints every 2048 samples",
+                       f"chirp targets, checkpoints every {args.diff_ckpt_stride} samples",
            "forward_ms": fwd_ms, "backward_ms": bwd_ms,
            "forward_updates_per_s": upd / (fwd_ms * 1e-3),
            "backward_updates_per_s": upd / (bwd_ms * 1e-3),
