@@ -13,6 +13,11 @@
 // direction on ties).  One workgroup per candidate slot walks the shifts; its threads
 // split the directions and meet in a wave-shuffle + LDS arg-max.  A (candidate,
 // shift) whose samples leave [0, n) for any direction is marked NaN / -1.
+// Per shift the workgroup first copies, for every detector J, the kStage samples of
+// z_J centred on the shifted candidate sample into LDS; a direction whose relative
+// delay tau[p][J] - tau[p][I] falls inside that window reads LDS, any other reads
+// global memory.  A thread keeps the delays and signal-plane columns of its first
+// kDirCache directions in registers across the shifts.
 #include <cmath>
 
 #include "internal.h"
@@ -21,6 +26,8 @@ namespace spiir {
 namespace {
 
 constexpr int kCohThreads = 256;
+constexpr int kStage = 256;      // staged samples per detector and shift
+constexpr int kDirCache = 4;     // directions per thread whose tables stay in registers
 
 struct Best {
     float v;
@@ -32,6 +39,28 @@ __device__ __forceinline__ Best better(Best a, Best b) {
 }
 
 template <int ND>
+struct Dir {
+    int32_t rel[ND];     // tau[p][J] - tau[p][I]
+    float u0[ND], u1[ND];
+};
+
+template <int ND>
+__device__ __forceinline__ Dir<ND> load_dir(const int32_t *__restrict__ tau,
+                                            const float *__restrict__ U, int p, int I) {
+    Dir<ND> d;
+    const int32_t *tp = tau + (int64_t)p * ND;
+    const float *Up = U + (int64_t)p * ND * ND;
+    const int tI = tp[I];
+#pragma unroll
+    for (int J = 0; J < ND; ++J) {
+        d.rel[J] = tp[J] - tI;
+        d.u0[J] = Up[J * ND + 0];
+        d.u1[J] = Up[J * ND + 1];
+    }
+    return d;
+}
+
+template <int ND>
 __global__ __launch_bounds__(kCohThreads) void coherent_kernel(
     const float2 *__restrict__ z, int32_t n_templates, int32_t n, const int32_t *__restrict__ index,
     int32_t n_win, const float *__restrict__ U, const int32_t *__restrict__ tau, int32_t n_pix,
@@ -40,6 +69,7 @@ __global__ __launch_bounds__(kCohThreads) void coherent_kernel(
     __shared__ Best wbest[kCohThreads / kWave];
     __shared__ float wnull[kCohThreads / kWave];
     __shared__ int wbad[kCohThreads / kWave];
+    __shared__ float2 stage[ND][kStage];
     const int64_t cand = blockIdx.x;   // (I, t, w)
     const int64_t row = cand / n_win;  // I * T + t
     const int t = (int)(row % n_templates);
@@ -57,6 +87,12 @@ __global__ __launch_bounds__(kCohThreads) void coherent_kernel(
     const float2 *zt[ND];
 #pragma unroll
     for (int J = 0; J < ND; ++J) zt[J] = z + ((int64_t)J * n_templates + t) * n;
+    Dir<ND> dc[kDirCache];
+#pragma unroll
+    for (int i = 0; i < kDirCache; ++i) {
+        const int p = threadIdx.x + i * kCohThreads;
+        if (p < n_pix) dc[i] = load_dir<ND>(tau, U, p, I);
+    }
     for (int k = 0; k < n_shift; ++k) {
         int base[ND];
 #pragma unroll
@@ -64,25 +100,30 @@ __global__ __launch_bounds__(kCohThreads) void coherent_kernel(
             const int r = J >= I ? J - I : J - I + ND;
             base[J] = c + shifts[k * ND + r] - shifts[k * ND];
         }
+        for (int e = threadIdx.x; e < ND * kStage; e += kCohThreads) {
+            const int J = e / kStage, o = e % kStage;
+            const int s = base[J] + o - kStage / 2;
+            stage[J][o] = (s >= 0 && s < n) ? zt[J][s] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
         Best best{-1.0f, INT32_MAX};
         float best_null = 0.0f;
         int bad = 0;
-        for (int p = threadIdx.x; p < n_pix; p += kCohThreads) {
-            const int32_t *tp = tau + (int64_t)p * ND;
-            const float *Up = U + (int64_t)p * ND * ND;
-            const int tI = tp[I];
+        auto eval = [&](const Dir<ND> &d, int p) {
             float c0r = 0.f, c0i = 0.f, c1r = 0.f, c1i = 0.f, tot = 0.f;
             bool ok = true;
 #pragma unroll
             for (int J = 0; J < ND; ++J) {
-                const int s = base[J] + tp[J] - tI;
-                ok = ok && s >= 0 && s < n;
-                const float2 v = (s >= 0 && s < n) ? zt[J][s] : make_float2(0.f, 0.f);
-                const float u0 = Up[J * ND + 0], u1 = Up[J * ND + 1];
-                c0r = fmaf(u0, v.x, c0r);
-                c0i = fmaf(u0, v.y, c0i);
-                c1r = fmaf(u1, v.x, c1r);
-                c1i = fmaf(u1, v.y, c1i);
+                const int s = base[J] + d.rel[J];
+                const bool in = s >= 0 && s < n;
+                ok = ok && in;
+                const int o = d.rel[J] + kStage / 2;   // staged entries are zero outside [0, n)
+                const float2 v = (o >= 0 && o < kStage) ? stage[J][o]
+                                                        : (in ? zt[J][s] : make_float2(0.f, 0.f));
+                c0r = fmaf(d.u0[J], v.x, c0r);
+                c0i = fmaf(d.u0[J], v.y, c0i);
+                c1r = fmaf(d.u1[J], v.x, c1r);
+                c1i = fmaf(d.u1[J], v.y, c1i);
                 tot = fmaf(v.x, v.x, fmaf(v.y, v.y, tot));
             }
             if (!ok) bad = 1;
@@ -91,7 +132,14 @@ __global__ __launch_bounds__(kCohThreads) void coherent_kernel(
             const Best nb = better(best, cur);
             if (nb.p == p) best_null = tot - rc;
             best = nb;
+        };
+#pragma unroll
+        for (int i = 0; i < kDirCache; ++i) {
+            const int p = threadIdx.x + i * kCohThreads;
+            if (p < n_pix) eval(dc[i], p);
         }
+        for (int p = threadIdx.x + kDirCache * kCohThreads; p < n_pix; p += kCohThreads)
+            eval(load_dir<ND>(tau, U, p, I), p);
         // arg-max over the workgroup (carrying the null power of the winner)
         for (int off = kWave / 2; off >= 1; off >>= 1) {
             const Best o{__shfl_xor(best.v, off), __shfl_xor(best.p, off)};
@@ -129,7 +177,7 @@ __global__ __launch_bounds__(kCohThreads) void coherent_kernel(
                 pix_out[o] = b.p;
             }
         }
-        __syncthreads();
+        __syncthreads();   // stage and wbest are rewritten by the next shift
     }
 }
 
