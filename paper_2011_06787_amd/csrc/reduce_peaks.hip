@@ -177,32 +177,59 @@ __global__ __launch_bounds__(kHistThreads) void hist_update_kernel(float *__rest
     }
 }
 
-// Trigger selection (Section II.C.1).  Pass 1: one thread per (detector, sample)
-// finds the template with the largest normalised SNR^2 (lowest template on ties)
-// and, above threshold, offers it to that template's window slot with a 64-bit
-// atomic max of (rho2 bits << 32 | ~sample): the largest rho2 wins, then the lowest
-// sample, whatever the order of the offers.  Pass 2 decodes the slots.
-__global__ void trigger_keys_kernel(const float2 *__restrict__ z, int32_t n_templates, int32_t n,
-                                    const float *__restrict__ weight, float thr2, int32_t window,
-                                    int32_t n_win, unsigned long long *__restrict__ keys) {
+// Trigger selection (Section II.C.1).  Pass 1: a workgroup covers S samples of one
+// detector and all templates: thread (sample s, group g) scans templates g, g +
+// 256/S, ... (a wave reads 64/S template rows of S consecutive samples; S = 32 for
+// long streams, 8 for short packets so that the launch still fills the chip), then
+// one thread per sample takes the largest normalised SNR^2 over the
+// groups (lowest template on ties) and, above threshold, offers it to that template's
+// window slot with a 64-bit atomic max of (rho2 bits << 32 | ~sample): the largest
+// rho2 wins, then the lowest sample, whatever the order of the offers.  Pass 2 decodes
+// the slots.
+constexpr int kTrigThreads = 256;
+
+template <int S>
+__global__ __launch_bounds__(kTrigThreads) void trigger_keys_kernel(
+    const float2 *__restrict__ z, int32_t n_templates, int32_t n, const float *__restrict__ weight,
+    float thr2, int32_t window, int32_t n_win, unsigned long long *__restrict__ keys) {
+    constexpr int kTrigGroups = kTrigThreads / S;
+    __shared__ float sbest[kTrigGroups][S];
+    __shared__ int sidx[kTrigGroups][S];
     const int det = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float2 *zd = z + (int64_t)det * n_templates * n + i;
+    const int sl = threadIdx.x % S, g = threadIdx.x / S;
+    const int i = blockIdx.x * S + sl;
     float best = -1.0f;
-    int bt = -1;
-    for (int t = 0; t < n_templates; ++t) {
-        const float2 v = zd[(int64_t)t * n];
-        const float r2 = __fmul_rn(abs2_rn(v.x, v.y), weight[t]);
-        if (r2 > best) {
-            best = r2;
-            bt = t;
+    int bt = INT32_MAX;
+    if (i < n) {
+        const float2 *zd = z + (int64_t)det * n_templates * n + i;
+        // increasing templates and a strict comparison: the lowest template of a tie
+#pragma unroll 4
+        for (int t = g; t < n_templates; t += kTrigGroups) {
+            const float2 v = zd[(int64_t)t * n];
+            const float r2 = __fmul_rn(abs2_rn(v.x, v.y), weight[t]);
+            if (r2 > best) {
+                best = r2;
+                bt = t;
+            }
         }
     }
-    if (bt >= 0 && best > thr2) {
-        const unsigned long long key =
-            ((unsigned long long)__float_as_uint(best) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
-        atomicMax(keys + ((int64_t)det * n_templates + bt) * n_win + i / window, key);
+    sbest[g][sl] = best;
+    sidx[g][sl] = bt;
+    __syncthreads();
+    if (threadIdx.x < S && i < n) {
+        for (int q = 1; q < kTrigGroups; ++q) {
+            const float v = sbest[q][sl];
+            const int t = sidx[q][sl];
+            if (v > best || (v == best && t < bt)) {
+                best = v;
+                bt = t;
+            }
+        }
+        if (bt != INT32_MAX && best > thr2) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(best) << 32) |
+                                           (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+            atomicMax(keys + ((int64_t)det * n_templates + bt) * n_win + i / window, key);
+        }
     }
 }
 
@@ -282,8 +309,12 @@ hipError_t launch_triggers(const float2 *z, int32_t n_det, int32_t n_templates, 
     // clear the slots with a kernel (graph-safe)
     hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, work, count);
     const float thr2 = threshold * threshold;
-    hipLaunchKernelGGL(trigger_keys_kernel, dim3((n + 255) / 256, n_det), dim3(256), 0, s, z,
-                       n_templates, n, weight, thr2, window, n_win, work);
+    if ((int64_t)(n / 32) * n_det >= 1024)
+        hipLaunchKernelGGL(trigger_keys_kernel<32>, dim3((n + 31) / 32, n_det), dim3(kTrigThreads),
+                           0, s, z, n_templates, n, weight, thr2, window, n_win, work);
+    else
+        hipLaunchKernelGGL(trigger_keys_kernel<8>, dim3((n + 7) / 8, n_det), dim3(kTrigThreads),
+                           0, s, z, n_templates, n, weight, thr2, window, n_win, work);
     hipLaunchKernelGGL(trigger_decode_kernel, dim3((unsigned)blocks), dim3(256), 0, s, work, count,
                        snr, index);
     return hipGetLastError();
