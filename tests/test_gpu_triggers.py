@@ -9,7 +9,9 @@ import synth
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("D, T, n, window", [(1, 7, 1000, 256), (3, 40, 2048, 2048), (2, 3, 100, 7)])
+# the last case is long enough for the 32-samples-per-workgroup kernel (ragged tail)
+@pytest.mark.parametrize("D, T, n, window", [(1, 7, 1000, 256), (3, 40, 2048, 2048), (2, 3, 100, 7),
+                                             (2, 5, 20011, 512)])
 def test_triggers_bit_exact_on_seeded_series(gpu, D, T, n, window):
     import torch
     rng = np.random.default_rng(D * 100 + T)
