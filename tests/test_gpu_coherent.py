@@ -63,6 +63,26 @@ def test_coherent_matches_oracle_on_synthetic_series(gpu, D):
     print(f"D={D}: {n_ok} evaluations, {n_clear} with a clear best direction")
 
 
+def test_coherent_far_delays_read_outside_the_staged_window(gpu):
+    """Delays of up to +-200 samples: relative delays beyond the kernel's LDS window of
+    +-128 samples around the shifted candidate are read from global memory."""
+    import torch
+    from paper_2011_06787_amd import spiir
+    rng = np.random.default_rng(7)
+    D, T, n, W, P, K = 3, 2, 2000, 3, 200, 4
+    z = ((rng.standard_normal((D, T, n)) + 1j * rng.standard_normal((D, T, n)))).astype(np.complex64)
+    tab = synth.sky_tables(17, D, P, max_offset=200)
+    rel = tab.tau[:, :, None] - tab.tau[:, None, :]
+    assert np.abs(rel).max() > 128 and (np.abs(rel) <= 128).any()
+    sh = synth.time_shifts(D, K, step=25)
+    idx = rng.integers(500, 1500, size=(D, T, W)).astype(np.int32)
+    idx[1, 0, 2] = 250                 # some directions reach before the series
+    cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = spiir.coherent(cuda(z), cuda(idx), cuda(tab.U), cuda(tab.tau), cuda(sh))
+    n_ok, n_clear = _compare(out, z, idx, tab, sh)
+    print(f"far delays: {n_ok} evaluations, {n_clear} with a clear best direction")
+
+
 def test_coherent_end_to_end_from_the_filter_bank(gpu):
     # three detectors' SNR series from the bank (oracle for the oracle side, GPU scan for
     # the GPU side), candidates from the oracle's trigger selection
