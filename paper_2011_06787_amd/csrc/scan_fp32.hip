@@ -25,6 +25,7 @@
 // fixed set of resident waves, each with a host-planned list of equal total work in
 // which slices may be cut in time between two waves.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -216,6 +217,30 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, int red_
 #undef SPIIR_SUB_TILE
 }
 
+// Run fn(std::integral_constant<int, M>{}) for the wave-uniform filter count m in
+// 1..MAXM: a caller's whole sub-tile loop is compiled once per filter count, so the
+// loop makes no per-sub-tile dispatch (5% of the balanced kernel's time on the
+// realistic bank when the switch sat inside the loop).
+template <int MAXM, typename Fn>
+__device__ __forceinline__ void with_m(int m, Fn &&fn) {
+#define SPIIR_WITH_M(M)                                                                      \
+    case M:                                                                                  \
+        if constexpr (M <= MAXM) fn(std::integral_constant<int, M>{});                      \
+        break;
+    switch (m) {
+        SPIIR_WITH_M(1)
+        SPIIR_WITH_M(2)
+        SPIIR_WITH_M(3)
+        SPIIR_WITH_M(4)
+        SPIIR_WITH_M(5)
+        SPIIR_WITH_M(6)
+        SPIIR_WITH_M(7)
+        SPIIR_WITH_M(8)
+    default: break;
+    }
+#undef SPIIR_WITH_M
+}
+
 template <int MAXM>
 __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
@@ -274,21 +299,24 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
         load_window(win, xd, hd, hist_len, n0, T, threadIdx.x, blockDim.x);
         __syncthreads();
         if (!active) continue;
-        int s0 = 0;
-        for (; s0 + kSub <= T; s0 += kSub) {
-            sub_tile<MAXM, false>(win, red_sample, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
-                                  pout + n0 + s0);
-            const int e = n0 + s0 + kSub;
-            if (ck != nullptr && e % ckpt_stride == 0 && e < n) {
-                float2 *cs = ck + (int64_t)(e / ckpt_stride) * lanes_total;
+        const int full = T & ~(kSub - 1);
+        with_m<MAXM>(m, [&](auto mc) {
+            constexpr int M = decltype(mc)::value;
+            for (int s0 = 0; s0 < full; s0 += kSub) {
+                sub_tile_m<MAXM, M, false>(win, red_sample, lane, s0, kSub, ar, ai, br, bi, base,
+                                           yr, yi, pout + n0 + s0);
+                const int e = n0 + s0 + kSub;
+                if (ck != nullptr && e % ckpt_stride == 0 && e < n) {
+                    float2 *cs = ck + (int64_t)(e / ckpt_stride) * lanes_total;
 #pragma unroll
-                for (int j = 0; j < MAXM; ++j)
-                    if (j < m) cs[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+                    for (int j = 0; j < M; ++j)
+                        cs[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+                }
             }
-        }
-        if (s0 < T)
-            sub_tile<MAXM, true>(win, red_sample, lane, m, s0, T - s0, ar, ai, br, bi, base, yr, yi,
-                                 pout + n0 + s0);
+        });
+        if (full < T)
+            sub_tile<MAXM, true>(win, red_sample, lane, m, full, T - full, ar, ai, br, bi, base, yr,
+                                 yi, pout + n0 + full);
     }
     if (active) {
 #pragma unroll
@@ -512,18 +540,21 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
         }
         float2 *pout = partial + ((int64_t)det * n_slices + sg.slice) * part_stride;
         const int full_end = t1 == n ? (n & ~(kSub - 1)) : t1;
-        for (int s0 = t0; s0 < full_end; s0 += kSub) {
-            sub_tile<MAXM, false>(win, red_sample, lane, m, s0, kSub, ar, ai, br, bi, base, yr,
-                                  yi, pout + s0);
-            simd_step(peers, 20u * (uint32_t)m + 9u, lane);
-            const int eo = s0 + kSub;
-            if (ck != nullptr && eo % ckpt_stride == 0 && eo < n) {
-                float2 *cs = ck + (int64_t)(eo / ckpt_stride) * lanes_total;
+        with_m<MAXM>(m, [&](auto mc) {
+            constexpr int M = decltype(mc)::value;
+            for (int s0 = t0; s0 < full_end; s0 += kSub) {
+                sub_tile_m<MAXM, M, false>(win, red_sample, lane, s0, kSub, ar, ai, br, bi, base,
+                                           yr, yi, pout + s0);
+                simd_step(peers, 20u * (uint32_t)M + 9u, lane);
+                const int eo = s0 + kSub;
+                if (ck != nullptr && eo % ckpt_stride == 0 && eo < n) {
+                    float2 *cs = ck + (int64_t)(eo / ckpt_stride) * lanes_total;
 #pragma unroll
-                for (int j = 0; j < MAXM; ++j)
-                    if (j < m) cs[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+                    for (int j = 0; j < M; ++j)
+                        cs[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
+                }
             }
-        }
+        });
         if (t1 == n && full_end < n)
             sub_tile<MAXM, true>(win, red_sample, lane, m, full_end, n - full_end, ar, ai, br, bi,
                                  base, yr, yi, pout + full_end);
@@ -641,13 +672,16 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
         }
         lds_fence();  // window stores visible to every lane of the wave
         float2 *pout = partial + ((int64_t)det * n_slices + sidx) * part_stride + n0;
-        int s0 = 0;
-        for (; s0 + kSub <= T; s0 += kSub)
-            sub_tile<MAXM, false>(win, red_sample, lane, m, s0, kSub, ar, ai, br, bi, base, yr, yi,
-                                  pout + s0);
-        if (s0 < T)
-            sub_tile<MAXM, true>(win, red_sample, lane, m, s0, T - s0, ar, ai, br, bi, base, yr, yi,
-                                 pout + s0);
+        const int full = T & ~(kSub - 1);
+        with_m<MAXM>(m, [&](auto mc) {
+            constexpr int M = decltype(mc)::value;
+            for (int s0 = 0; s0 < full; s0 += kSub)
+                sub_tile_m<MAXM, M, false>(win, red_sample, lane, s0, kSub, ar, ai, br, bi, base,
+                                           yr, yi, pout + s0);
+        });
+        if (full < T)
+            sub_tile<MAXM, true>(win, red_sample, lane, m, full, T - full, ar, ai, br, bi, base, yr,
+                                 yi, pout + full);
 #pragma unroll
         for (int j = 0; j < MAXM; ++j)
             if (j < m)
