@@ -465,8 +465,14 @@ __device__ __forceinline__ int phi_sample(int32_t phi, int32_t n) {
 // slice runs first in its wave while the later part runs last in its own, so the
 // state hand-off between them rarely waits.  The window x[-hist_len, n) of the
 // workgroup's detector is loaded into LDS once for all its waves.
+// Waves per SIMD the balanced kernel must fit in registers: its planner places a
+// whole number of workgroups (one wave per SIMD each) on every compute unit, and the
+// best counts are 3 at 8 filters per lane and up to 4 at 2 or 4.
+constexpr int balanced_min_waves(int maxm) { return maxm >= 8 ? 3 : 4; }
+
 template <int MAXM>
-__global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_balanced_kernel(
+__global__ __launch_bounds__(kWave *kScanWaves) __attribute__((amdgpu_waves_per_eu(
+    balanced_min_waves(MAXM)))) void scan_fp32_balanced_kernel(
     const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
     float2 *__restrict__ state, const Slice *__restrict__ slices, int32_t n_slices,
     const Seg *__restrict__ segs, const int32_t *__restrict__ seg_off, int32_t waves_per_det,

@@ -62,3 +62,17 @@ def test_autotuner_picks_a_measured_candidate(gpu):
                                  block_candidates=[dict(block_len=128)])
     assert len(trials) == 4 and best in trials
     assert best.updates_per_s == max(t.updates_per_s for t in trials)
+
+
+@pytest.mark.parametrize("filters_per_lane, balance_wgs", [(8, 3), (4, 4), (2, 4)])
+def test_balanced_plan_gets_the_requested_workgroups_per_cu(gpu, filters_per_lane, balance_wgs):
+    """The planner clamps its workgroups per compute unit to the kernel's occupancy; at
+    the batching bank's size the requested count must survive (the register budget of
+    the balanced kernel is what allows it)."""
+    import torch
+    w = synth.batching()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    with gpu.SpiirBank.from_bank(w.bank, n_detectors=w.n_det, max_chunk=w.chunk,
+                                 filters_per_lane=filters_per_lane, time_tile=0,
+                                 balance_wgs=balance_wgs) as sb:
+        assert sb.info.balance_waves == balance_wgs * max(1, cus // w.n_det) * 4
