@@ -76,3 +76,34 @@ def test_balanced_plan_gets_the_requested_workgroups_per_cu(gpu, filters_per_lan
                                  filters_per_lane=filters_per_lane, time_tile=0,
                                  balance_wgs=balance_wgs) as sb:
         assert sb.info.balance_waves == balance_wgs * max(1, cus // w.n_det) * 4
+
+
+def test_two_graph_instances_replayed_in_turn_match_eager(gpu):
+    """Two captures of the same bank's packet, each with its own input buffer, replayed
+    alternately on one stream (the bank's state and hand-off epochs live on the device):
+    every packet equals the eager result of a second bank fed the same packets."""
+    import torch
+    w = synth.batching()
+    bank, D, chunk = w.bank, w.n_det, w.chunk
+    n_packets = 6
+    x = torch.from_numpy(w.input()[:, :n_packets * chunk]).cuda()
+    packets = [x[:, i * chunk:(i + 1) * chunk].contiguous() for i in range(n_packets)]
+    T = bank.n_templates
+    kw = dict(n_detectors=D, max_chunk=chunk, filters_per_lane=8, time_tile=0, balance_wgs=3)
+    with gpu.SpiirBank.from_bank(bank, **kw) as g_bank, gpu.SpiirBank.from_bank(bank, **kw) as e_bank:
+        zg = torch.empty((D, T, chunk), dtype=torch.complex64, device="cuda")
+        pg = torch.empty((D, T, 1), dtype=torch.float32, device="cuda")
+        ag = torch.empty((D, T, 1), dtype=torch.int32, device="cuda")
+        sx = [torch.empty((D, chunk), dtype=torch.float32, device="cuda") for _ in range(2)]
+        graphs = [torch.cuda.CUDAGraph() for _ in range(2)]
+        for g, s in zip(graphs, sx):
+            with torch.cuda.graph(g):
+                g_bank.filter_chunk(s, zg, pg, ag)
+        torch.cuda.synchronize()
+        for i in range(n_packets):
+            sx[i % 2].copy_(packets[i])
+            graphs[i % 2].replay()
+            ze, pe, ae = e_bank.filter_chunk(packets[i])
+            torch.cuda.synchronize()
+            assert torch.equal(zg, ze) and torch.equal(pg, pe) and torch.equal(ag, ae), f"packet {i}"
+        assert g_bank.refresh_info().scan_wait_timeouts == 0
