@@ -95,6 +95,23 @@ def test_filters_per_lane_and_slice_boundaries(gpu, fpl, time_tile, balance_wgs)
     check_peaks(pk[0], am[0], z, z_ref, 500)
 
 
+@pytest.mark.parametrize("time_tile, balance_wgs", [(0, 0), (0, 2), (256, 0)])
+def test_bank_without_filters(gpu, time_tile, balance_wgs):
+    # every template empty (F = 0): the SNR is zero and each window's peak is 0 at its
+    # first sample, as the oracle's float32 decision gives (lowest index on ties)
+    rng = np.random.default_rng(310)
+    bank = synth.draw_filters(rng, np.array([0, 0, 0]))
+    assert bank.n_filters == 0
+    x = rng.standard_normal((2, 700)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    z, pk, am = run_stream(gpu, bank, x, 300, peak_window=100, time_tile=time_tile,
+                           balance_wgs=balance_wgs)
+    assert z.shape == z_ref.shape and np.all(z == 0) and np.all(z_ref == 0)
+    for c, lo in enumerate(range(0, 700, 300)):
+        p_ref, a_ref = oracle.peaks_f32(z_ref[..., lo:lo + 300].astype(np.complex64), 100)
+        assert np.array_equal(pk[c], p_ref) and np.array_equal(am[c], a_ref)
+
+
 def test_delay_extremes_and_history(gpu):
     # delays 0 and exactly max_delay; history longer than the chunk; max_delay > largest delay
     rng = np.random.default_rng(300)
