@@ -25,6 +25,25 @@ def test_triggers_bit_exact_on_seeded_series(gpu, D, T, n, window):
     assert (idx_ref >= 0).sum() > 0
 
 
+@pytest.mark.parametrize("D, T, n, window", [(1, 7, 1000, 256), (2, 5, 20011, 512)])
+@pytest.mark.parametrize("threshold", [0.0, 1.0e4])
+def test_triggers_threshold_extremes(gpu, D, T, n, window, threshold):
+    # threshold 0: every window of every template keeps its loudest sample; a threshold
+    # no sample reaches: no candidate anywhere (index -1, snr 0)
+    import torch
+    rng = np.random.default_rng(D * 1000 + T)
+    z = (rng.standard_normal((D, T, n)) + 1j * rng.standard_normal((D, T, n))).astype(np.complex64)
+    w = rng.uniform(0.4, 1.6, size=T).astype(np.float32)
+    snr, idx = gpu.triggers(torch.from_numpy(z).cuda(), torch.from_numpy(w).cuda(), threshold, window)
+    snr_ref, idx_ref = oracle.triggers(z, w, threshold, window)
+    assert np.array_equal(idx.cpu().numpy(), idx_ref)
+    assert np.array_equal(snr.cpu().numpy(), snr_ref)
+    if threshold > 0:
+        assert np.all(idx_ref == -1) and np.all(snr_ref == 0)
+    else:
+        assert (idx_ref >= 0).any()
+
+
 def test_noise_power_matches_oracle(gpu):
     w = synth.tiny()
     rng = np.random.default_rng(5)
