@@ -56,6 +56,64 @@ def measured_traffic(kernel_src, per_launch_key):
     return rec.get(per_launch_key)
 
 
+def argmax_report(gpu_peak, gpu_arg, z_gpu, z_ref, window):
+    """Peak/argmax agreement with the FP64 oracle, per window (the margin-aware rule).
+
+    Where the oracle's gap between the best and second-best |z| of a window exceeds
+    twice the largest pointwise |z_gpu - z_ref| there (plus 4 float32 ulps of the
+    peak), no rounding error can reorder them and the indices must be equal ("clear");
+    elsewhere ("ambiguous") the GPU index must point at a sample whose oracle |z| lies
+    within that band of the oracle maximum ("near_max").  Rows are processed in blocks
+    to bound host memory.  Returns counts, never raises."""
+    import oracle
+    z_gpu = np.asarray(z_gpu)
+    lead, n = z_ref.shape[:-1], z_ref.shape[-1]
+    rows = int(np.prod(lead))
+    zg = z_gpu.reshape(rows, n)
+    zr = z_ref.reshape(rows, n)
+    pg = np.asarray(gpu_peak, np.float64).reshape(rows, -1)
+    ag = np.asarray(gpu_arg).reshape(rows, -1).astype(np.int64)
+    n_win = (n + window - 1) // window
+    pad = n_win * window - n
+    tot = clear = equal = amb = near = 0
+    peak_rel = 0.0
+    for r0 in range(0, rows, 64):
+        r1 = min(rows, r0 + 64)
+        p_ref, a_ref, margin = oracle.peaks(zr[r0:r1], window)
+        diff = np.abs(zg[r0:r1].astype(np.complex128) - zr[r0:r1])
+        zabs = np.abs(zr[r0:r1])
+        if pad:
+            diff = np.concatenate([diff, np.zeros((r1 - r0, pad))], axis=1)
+            zabs = np.concatenate([zabs, np.zeros((r1 - r0, pad))], axis=1)
+        err = diff.reshape(r1 - r0, n_win, window).max(axis=-1)
+        zabs = zabs.reshape(r1 - r0, n_win, window)
+        slack = 2.0 * err + 4.0 * np.finfo(np.float32).eps * p_ref
+        strict = margin * p_ref > slack
+        a = ag[r0:r1]
+        chosen = np.take_along_axis(zabs, a[..., None], axis=-1)[..., 0]
+        tot += strict.size
+        clear += int(strict.sum())
+        equal += int((a[strict] == a_ref[strict]).sum())
+        amb += int((~strict).sum())
+        near += int((chosen[~strict] >= p_ref[~strict] - slack[~strict]).sum())
+        peak_rel = max(peak_rel, float(np.max(np.abs(pg[r0:r1] - p_ref) / np.maximum(p_ref, 1e-300))))
+    return {"windows": tot, "clear_margin": clear, "equal_under_clear_margin": equal,
+            "ambiguous": amb, "ambiguous_near_max": near, "peak_rel_err_max": peak_rel,
+            "bit_exact_where_clear": equal == clear, "window": int(window)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -75,15 +133,19 @@ def parse():
     p.add_argument("--precision-only", action="store_true")
     p.add_argument("--precision-reps", type=int, default=5)
     p.add_argument("--block-len", type=int, default=0, help="0 = sweep 64, 128, 256")
+    p.add_argument("--precision-check-templates", type=int, default=1024,
+                   help="templates compared with the oracle in the precision section (all by default)")
     p.add_argument("--no-batching", action="store_true",
                    help="skip the batching workload (16384 templates, 3 detectors, 0.25-s packets)")
     p.add_argument("--batching-only", action="store_true")
     p.add_argument("--batching-packets", type=int, default=240)
     p.add_argument("--batching-graphs", type=int, default=1,
                    help="captured graph instances replayed in turn, each with its own input buffer")
-    p.add_argument("--diff-ckpt-stride", type=int, default=512,
-                   help="differentiation: samples per checkpoint segment (multiple of 128; "
-                        "512 gave the fastest forward + backward on this workload)")
+    p.add_argument("--diff-ckpt-stride", type=int, default=2048,
+                   help="differentiation: samples per checkpoint segment (multiple of 128); the "
+                        "workload's own stride is 2048")
+    p.add_argument("--diff-extra-strides", type=str, default="512",
+                   help="comma-separated extra checkpoint strides timed beside the main one")
     p.add_argument("--no-tune", action="store_true",
                    help="skip the autotuners (batching schedule, precision FP32 schedule)")
     p.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
@@ -132,9 +194,16 @@ def precision_comparison(args, dev):
     D, N, F, T = w.n_det, w.n_samples, bank.n_filters, bank.n_templates
     x = torch.from_numpy(x_host).to(dev)
     z = torch.empty((D, T, N), dtype=torch.complex64, device=dev)
-    pick = sorted(set([0, T - 1]) | set(np.random.default_rng(5).choice(T, 6, replace=False).tolist()))
+    if args.precision_check_templates >= T:
+        pick = list(range(T))
+    else:
+        pick = sorted(set([0, T - 1]) | set(np.random.default_rng(5).choice(
+            T, max(0, args.precision_check_templates - 2), replace=False).tolist()))
+    t_ref = time.perf_counter()
     z_ref = oracle.filter(bank.subset(pick), x_host)
+    log(f"precision: oracle over {len(pick)} templates took {time.perf_counter() - t_ref:.1f} s")
     idx = torch.tensor(pick, device=dev)
+    window = 2048
     out = {"workload": "precision: 1024 templates x U{200..800} filters (521,135), 3 detector "
                        "streams of 32 s at 2048 Hz, one packet per stream",
            "updates_per_pass": F * D * N}
@@ -168,16 +237,26 @@ def precision_comparison(args, dev):
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.precision_reps
         kern_ms, launches = sb.kernel_time()
-        zsel = z.index_select(1, idx).cpu().numpy()
-        err = oracle.rel_err(zsel, z_ref)
+        # the library's own peak kernel on the series, one window per second
+        pk, am = spiir.peaks(z, window)
+        zsel = (z if len(pick) == T else z.index_select(1, idx)).cpu().numpy()
+        pk = (pk if len(pick) == T else pk.index_select(1, idx)).cpu().numpy()
+        am = (am if len(pick) == T else am.index_select(1, idx)).cpu().numpy()
+        err = np.concatenate([oracle.rel_err(zsel[:, t0:t0 + 64], z_ref[:, t0:t0 + 64]).ravel()
+                              for t0 in range(0, len(pick), 64)])
+        amx = argmax_report(pk, am, zsel, z_ref, window)
+        del zsel
         info = sb.refresh_info()
         out[name] = {"updates_per_s": F * D * N / wall, "ms_per_pass": wall * 1e3,
                      "kernel_ms": kern_ms / max(launches, 1),
                      "rel_err_max": float(err.max()), "rel_err_median": float(np.median(err)),
+                     "templates_checked": len(pick), "argmax": amx,
                      "create_s": t_create, "device_bytes": info.device_bytes,
                      "long_pole_filters": info.n_long_pole}
         log(f"precision {name}: {wall * 1e3:.2f} ms/pass, {F * D * N / wall:.4g} upd/s, "
-            f"rel err max {err.max():.2e}, create {t_create:.1f} s")
+            f"rel err max {err.max():.2e}, argmax {amx['equal_under_clear_margin']}/"
+            f"{amx['clear_margin']} equal where clear, {amx['ambiguous']} ambiguous, "
+            f"create {t_create:.1f} s")
         sb.close()
         del sb
         torch.cuda.empty_cache()
@@ -242,10 +321,12 @@ def batching_run(args, dev):
     torch.cuda.synchronize()
     sb.reset()
     torch.cuda.synchronize()
-    pick = sorted(set([0, T - 1]) | set(np.random.default_rng(3).choice(T, 6, replace=False).tolist()))
+    pick = sorted(set([0, T - 1]) | set(np.random.default_rng(3).choice(T, 62, replace=False).tolist()))
     idx = torch.tensor(pick, device=dev)
     n_check = min(8, n_packets)
     zsel = torch.empty((D, len(pick), n_check * chunk), dtype=torch.complex64, device=dev)
+    psel = torch.empty((D, len(pick), n_check), dtype=torch.float32, device=dev)
+    asel = torch.empty((D, len(pick), n_check), dtype=torch.int32, device=dev)
     # the gather of the checked templates runs once before timing: the first launch of a
     # kernel loads its code object, which would stall the host inside the timed loop
     zsel[:, :, :chunk] = z.index_select(1, idx)
@@ -260,11 +341,15 @@ def batching_run(args, dev):
         evs[i][1].record()
         if i < n_check:
             zsel[:, :, i * chunk:(i + 1) * chunk] = z.index_select(1, idx)
+            psel[:, :, i] = pk[:, :, 0].index_select(1, idx)
+            asel[:, :, i] = am[:, :, 0].index_select(1, idx)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     z_ref = oracle.filter(bank.subset(pick), x_host[:, :n_check * chunk])
-    err = oracle.rel_err(zsel.cpu().numpy(), z_ref)
+    zg = zsel.cpu().numpy()
+    err = oracle.rel_err(zg, z_ref)
+    amx = argmax_report(psel.cpu().numpy(), asel.cpu().numpy(), zg, z_ref, chunk)
     info = sb.refresh_info()
     out.update({
         "mode": best_mode, "options": best_opts, "graph": True, "graph_instances": n_graphs,
@@ -277,7 +362,7 @@ def batching_run(args, dev):
         # difference to the loop's wall clock is host time the GPU waited for
         "gpu_span_ms": float(evs[0][0].elapsed_time(evs[-1][1])),
         "wall_ms": wall * 1e3,
-        "rel_err_max": float(err.max()), "templates_checked": len(pick),
+        "rel_err_max": float(err.max()), "templates_checked": len(pick), "argmax": amx,
         "packets_checked": n_check, "device_bytes": info.device_bytes,
         "wait_timeouts": info.scan_wait_timeouts,
     })
@@ -349,6 +434,34 @@ def differentiation_run(args, dev):
         f"grad rel err a {out['grad_a_rel_err']:.2e} b {out['grad_b_rel_err']:.2e}")
     sb.close()
     del sb
+    torch.cuda.empty_cache()
+    # other checkpoint strides: timing only (same gradients up to rounding)
+    extra = {}
+    for stride in [int(s) for s in args.diff_extra_strides.split(",") if s.strip()]:
+        if stride == args.diff_ckpt_stride:
+            continue
+        with spiir.SpiirBank.from_bank(bank, max_chunk=n, ckpt_stride=stride,
+                                       filters_per_lane=args.diff_filters_per_lane) as sx:
+            sx.set_coeffs(a, b)
+            z2, ck2 = sx.forward(x)
+            ga2, gb2 = sx.backward(x, gz, ck2)
+            torch.cuda.synchronize()
+            e[0].record()
+            for _ in range(reps):
+                z2, ck2 = sx.forward(x, z2, ck2)
+            e[1].record()
+            for _ in range(reps):
+                ga2, gb2 = sx.backward(x, gz, ck2, ga2, gb2)
+            e[2].record()
+            torch.cuda.synchronize()
+            extra[str(stride)] = {"forward_ms": e[0].elapsed_time(e[1]) / reps,
+                                  "backward_ms": e[1].elapsed_time(e[2]) / reps,
+                                  "grad_b_rel_to_main": rel(gb2.cpu().numpy(), gb.cpu().numpy()),
+                                  "checkpoint_bytes": int(ck2.numel() * 8)}
+            log(f"differentiation, checkpoints every {stride}: forward "
+                f"{extra[str(stride)]['forward_ms']:.3f} ms, backward {extra[str(stride)]['backward_ms']:.3f} ms")
+    if extra:
+        out["other_ckpt_strides"] = extra
     torch.cuda.empty_cache()
     return out
 
@@ -525,12 +638,15 @@ def main():
     ms_step = elapsed * 1e3 / max(args.steps, 1)
     kern_avg_s = kern_ms / 1e3 / max(launches, 1)
     achieved_tflops = FLOP_PER_UPDATE * updates_per_step / kern_avg_s / 1e12
-    # algorithmic HBM bytes of one scan launch: coefficients (a, b: 8 B each, d: 4 B),
-    # state read + write (16 B) per filter and detector, input window per detector,
-    # and the slice partial sums written (8 B per slice per sample)
+    # algorithmic HBM bytes of one packet: coefficients (a, b: 8 B each, d: 4 B) per
+    # filter, state read + write (16 B) per filter and detector, the packet's input
+    # (4 B per sample and detector), the SNR series (8 B per template, sample and
+    # detector) and the peaks (8 B per template, window and detector)
     info = sb.info
-    alg_bytes = F * 20 + F * D * 16 + D * (chunk + info.max_delay) * 4 + \
-        D * info.n_slices * chunk * 8
+    alg_bytes = F * 20 + F * D * 16 + D * chunk * 4 + D * T * chunk * 8 + D * T * 8
+    # not algorithmic: partial sums of the filter groups, written by the scan and read by
+    # the template sum (8 B per group, sample and detector)
+    partial_bytes = D * info.n_slices * chunk * 8
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} updates/s; "
         f"scan kernel {kern_avg_s * 1e3:.3f} ms avg over {launches} launches")
 
@@ -568,41 +684,29 @@ def main():
                                  / (PEAK_FP32_TFLOPS * 1e12 / 2),
             "kernel_ms_avg": kern_avg_s * 1e3,
             "flop_per_launch": FLOP_PER_UPDATE * updates_per_step,
-            "alg_bytes_per_launch": alg_bytes,
-            "alg_hbm_GBps": alg_bytes / kern_avg_s / 1e9,
-            "hbm_frac": alg_bytes / kern_avg_s / 1e9 / PEAK_HBM_GBS,
+            "alg_bytes_per_packet": alg_bytes,
+            "alg_hbm_GBps_per_packet": alg_bytes / (ms_step * 1e-3) / 1e9,
+            "hbm_frac": alg_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "partial_bytes_per_launch": partial_bytes,
             "traffic": measured_traffic("scan_fp32.hip", "hbm_bytes_per_launch"),
         },
     }
 
-    if not args.no_check:
-        # relative SNR error vs the FP64 oracle on seeded templates over the whole stream
-        import oracle
-        pick = sorted(set([0, T - 1]) | set(np.random.default_rng(1).choice(T, 6, replace=False).tolist()))
-        idx = torch.tensor(pick, device=dev)
-        sb.reset()
-        zsel = torch.empty((D, len(pick), x_host.shape[1]), dtype=torch.complex64, device=dev)
-        for i in range(n_chunks):
-            step(i)
-            zsel[:, :, i * chunk:(i + 1) * chunk] = z.index_select(1, idx)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        z_ref = oracle.filter(bank.subset(pick), x_host)
-        log(f"oracle check of {len(pick)} templates took {time.perf_counter() - t1:.1f} s")
-        err = oracle.rel_err(zsel.cpu().numpy(), z_ref)
-        result["rel_err"] = {"max": float(err.max()), "median": float(np.median(err)),
-                             "templates_checked": len(pick), "tolerance": 1e-4}
-
+    z_ref_all = None
     if not args.no_cpu_baseline:
         import oracle
-        sub = bank.subset(range(min(args.cpu_templates, T)))
+        n_cpu = min(args.cpu_templates, T)
+        sub = bank.subset(range(n_cpu))
         cores = oracle.threads()
         t1 = time.perf_counter()
-        oracle.filter(sub, x_host)
+        z_ref_cpu = oracle.filter(sub, x_host)
         dt = time.perf_counter() - t1
+        if n_cpu == T:
+            z_ref_all = z_ref_cpu          # reused below: the GPU stream is checked against it
+        del z_ref_cpu
         upd = sub.n_filters * D * x_host.shape[1]
         # one thread on a 1/64 slice of the same work: the per-core rate
-        one = bank.subset(range(max(1, min(args.cpu_templates, T) // 64)))
+        one = bank.subset(range(max(1, n_cpu // 64)))
         oracle.set_threads(1)
         t2 = time.perf_counter()
         oracle.filter(one, x_host)
@@ -613,10 +717,47 @@ def main():
             "kind": "oracle",
             "sample": f"FP64 oracle, first {sub.n_templates} templates ({sub.n_filters} filters) "
                       f"of the same bank over the same 64-s stream, {dt:.1f} s wall",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "threads": cores,
             "per_core_value": one.n_filters * D * x_host.shape[1] / dt1,
             "per_core_sample": f"1 thread, first {one.n_templates} templates ({one.n_filters} "
                                f"filters), {dt1:.1f} s wall",
         }
+        log(f"cpu baseline: {upd / dt:.4g} updates/s on {cores} threads ({cpu_model()})")
+
+    if not args.no_check:
+        # relative SNR error and argmax agreement vs the FP64 oracle over the whole stream:
+        # every template when the CPU-baseline leg computed them all, else seeded templates
+        import oracle
+        if z_ref_all is not None:
+            pick = list(range(T))
+            z_ref = z_ref_all
+        else:
+            pick = sorted(set([0, T - 1]) | set(np.random.default_rng(1).choice(T, 6, replace=False).tolist()))
+            z_ref = oracle.filter(bank.subset(pick), x_host)
+        idx = torch.tensor(pick, device=dev)
+        sb.reset()
+        zsel = torch.empty((D, len(pick), x_host.shape[1]), dtype=torch.complex64, device=dev)
+        psel = torch.empty((D, len(pick), n_chunks), dtype=torch.float32, device=dev)
+        asel = torch.empty((D, len(pick), n_chunks), dtype=torch.int32, device=dev)
+        for i in range(n_chunks):
+            step(i)
+            zsel[:, :, i * chunk:(i + 1) * chunk] = z.index_select(1, idx)
+            psel[:, :, i] = peak[:, :, 0].index_select(1, idx)
+            asel[:, :, i] = amax[:, :, 0].index_select(1, idx)
+        torch.cuda.synchronize()
+        zg = zsel.cpu().numpy()
+        del zsel
+        err = oracle.rel_err(zg, z_ref)
+        result["rel_err"] = {"max": float(err.max()), "median": float(np.median(err)),
+                             "templates_checked": len(pick), "detectors": D,
+                             "samples_per_template": int(x_host.shape[1]), "tolerance": 1e-4}
+        result["argmax"] = argmax_report(psel.cpu().numpy(), asel.cpu().numpy(), zg, z_ref, chunk)
+        log(f"oracle check: {len(pick)} templates, rel err max {err.max():.3e}, argmax "
+            f"{result['argmax']['equal_under_clear_margin']}/{result['argmax']['clear_margin']} equal "
+            f"where clear, {result['argmax']['ambiguous']} ambiguous")
+        del zg, z_ref, z_ref_all
+    info = sb.refresh_info()
+    result["scan_wait_timeouts"] = info.scan_wait_timeouts
     sb.close()
     del sb
     torch.cuda.empty_cache()

@@ -66,7 +66,7 @@ typedef struct {
     int32_t mode;             /* spiir_mode */
     int32_t filters_per_lane; /* FP32 scan: filters held per GPU lane, 2, 4 or 8; 0 = 4 */
     int32_t time_tile;        /* FP32 scan schedule.  -1 or 0: one wave per filter group
-                                 walks the whole packet (see queue_wgs).  16..4096
+                                 walks the whole packet (see balance_wgs).  16..4096
                                  (multiple of 16): the persistent work-queue scan with
                                  packets cut into time tiles of this many samples */
     int32_t block_len;        /* block form: time-block length L, 64, 128 or 256; 0 = 128 */
@@ -80,12 +80,24 @@ typedef struct {
                                  capped by what fits, used when a packet of max_chunk
                                  samples and its history fit one LDS window: every wave
                                  gets an equal share of the work, filter groups being
-                                 cut in time between two waves where needed */
+                                 cut in time between two waves where needed.  Every
+                                 planned workgroup must be resident at once (the count
+                                 is clamped to the kernel's occupancy); waves that
+                                 share the GPU with other work may make a hand-off wait
+                                 hit its bound (see wait_spins) */
+    int32_t wait_spins;       /* FP32 scan, persistent or balanced schedule: bound of a wait
+                                 for the state another wave hands over, in polls of about
+                                 128 clocks; 0 = 4194304.  A wait that hits the bound lets
+                                 the wave go on with a stale state: the library counts it
+                                 (spiir_bank_info.scan_wait_timeouts) and every later
+                                 spiir_filter_chunk / spiir_forward / spiir_backward on the
+                                 bank returns SPIIR_E_STATE until spiir_bank_reset.  Small
+                                 values exist to test that path */
 } spiir_opts;
 
 /* Fill `opts` with defaults: 1 detector, max_chunk 2048, max_delay 0 (from the bank),
  * one peak window per packet, FP32 scan, 4 filters per lane, no time split, no balanced
- * schedule, L = 128, 0.999, checkpoint stride 2048. */
+ * schedule, L = 128, 0.999, checkpoint stride 2048, wait bound 4194304 polls. */
 void spiir_opts_default(spiir_opts *opts);
 
 /*
@@ -110,7 +122,9 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
 spiir_status spiir_bank_destroy(spiir_bank *bank);
 
 /* Zero the filter state and the input history of every detector: the next packet
- * is the start of a new stream. */
+ * is the start of a new stream.  Also clears the count of hand-off waits that hit their
+ * bound (after waiting for the bank's last stream and `stream`, so that no earlier launch
+ * can raise it afterwards). */
 spiir_status spiir_bank_reset(spiir_bank *bank, void *stream);
 
 /* Shape of a bank, for callers sizing their buffers. */
@@ -124,8 +138,9 @@ typedef struct {
     int32_t scan_waves;       /* grid of the persistent scan */
     int32_t block_len;
     int32_t n_long_pole;      /* block form: filters carried in FP64 */
-    int32_t scan_wait_timeouts; /* state hand-off waits (persistent or balanced scan) that hit their bound
-                                   (results of those packets are invalid); 0 normally */
+    int32_t scan_wait_timeouts; /* state hand-off waits (persistent or balanced scan) that hit their
+                                   bound since creation or the last reset: the stream's results
+                                   from that packet on are invalid; 0 normally */
     int32_t balance_waves;    /* waves per detector of the balanced schedule; 0 when the
                                  scan does not use it */
 } spiir_bank_info;
@@ -145,6 +160,8 @@ spiir_status spiir_bank_get_info(const spiir_bank *bank, spiir_bank_info *info);
  *           among equal |z|^2 the lowest index.  |z|^2 is re*re + im*im rounded
  *           in float32 without fused multiply-add, and peak = sqrtf of it.
  * peak and argmax must both be given or both be NULL.
+ * Returns SPIIR_E_STATE, enqueueing nothing, once an earlier launch on the bank had a
+ * state hand-off wait hit its bound (see spiir_opts.wait_spins), until spiir_bank_reset.
  */
 spiir_status spiir_filter_chunk(spiir_bank *bank, const float *x, int32_t n, float *z,
                                 float *peak, int32_t *argmax, void *stream);

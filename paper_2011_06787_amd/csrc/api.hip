@@ -55,6 +55,18 @@ spiir_status dev_alloc(spiir::Bank &bk, T **ptr, int64_t count) {
 void free_all(spiir::Bank &bk) {
     for (void *p : bk.allocations) (void)hipFree(p);
     bk.allocations.clear();
+    if (bk.h_wait_flag != nullptr) (void)hipHostFree(bk.h_wait_flag);
+    bk.h_wait_flag = bk.d_wait_flag = nullptr;
+}
+
+// A state hand-off wait of an earlier launch hit its bound: the waiting wave went on
+// with a stale state, so the stream's results are invalid until the next reset.
+spiir_status check_waits(const spiir::Bank &bk) {
+    if (bk.h_wait_flag != nullptr && __atomic_load_n(bk.h_wait_flag, __ATOMIC_ACQUIRE) != 0u)
+        return fail(SPIIR_E_STATE,
+                    "a state hand-off wait of an earlier FP32 scan launch hit its bound "
+                    "(wait_spins); the stream's results are invalid until spiir_bank_reset");
+    return SPIIR_OK;
 }
 
 void release_events(spiir::Bank &bk) {
@@ -328,6 +340,7 @@ void spiir_opts_default(spiir_opts *opts) {
     opts->long_pole_abs_a = 0.999;
     opts->ckpt_stride = 2048;
     opts->balance_wgs = 0;
+    opts->wait_spins = 0;
 }
 
 const char *spiir_last_error(void) { return g_error.c_str(); }
@@ -380,6 +393,7 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
             return fail(SPIIR_E_INVAL, "time_tile must be -1, 0 or a multiple of 16 in [16, 4096]");
         if (opts.balance_wgs < 0 || opts.balance_wgs > 8)
             return fail(SPIIR_E_INVAL, "balance_wgs must be in [0, 8]");
+        if (opts.wait_spins < 0) return fail(SPIIR_E_INVAL, "wait_spins must be >= 0");
         int32_t dmax = 0;
         for (int64_t k = 0; k < F; ++k) {
             const double ar = a[2 * k], ai = a[2 * k + 1], br = b[2 * k], bi = b[2 * k + 1];
@@ -417,6 +431,7 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
                          (int64_t)bk.max_chunk + hist_len + spiir::kSub <= spiir::kWindowFloats;
         bk.block_len = block_len;
         bk.ckpt_stride = ckpt_stride;
+        if (opts.wait_spins > 0) bk.wait_spins = (uint32_t)opts.wait_spins;
         bk.h_offsets.assign(offsets, offsets + n_templates + 1);
         if (F > 0) {
             bk.h_a.assign(a, a + 2 * F);
@@ -444,6 +459,22 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
                 }
             }
         } else if (st == SPIIR_OK) {
+            // the flag a bounded hand-off wait raises when it gives up, in pinned host
+            // memory so that later calls read it without synchronising
+            void *hp = nullptr, *dp = nullptr;
+            if (hipHostMalloc(&hp, 64, hipHostMallocMapped) != hipSuccess) {
+                (void)hipGetLastError();
+                st = fail(SPIIR_E_NOMEM, "hipHostMalloc of the wait flag failed");
+            } else {
+                bk.h_wait_flag = static_cast<uint32_t *>(hp);
+                *bk.h_wait_flag = 0u;
+                const hipError_t e = hipHostGetDevicePointer(&dp, hp, 0);
+                if (e != hipSuccess)
+                    st = fail(SPIIR_E_HIP, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
+                bk.d_wait_flag = static_cast<uint32_t *>(dp);
+            }
+        }
+        if (st == SPIIR_OK && bk.mode != SPIIR_MODE_BF16_BLOCK) {
             st = plan_scan(bk, offsets, a, b, delay, s);
             if (st == SPIIR_OK) {
                 hipError_t e = spiir::prepare_scan_fp32(bk);
@@ -539,9 +570,20 @@ spiir_status spiir_bank_kernel_time(spiir_bank *h, double *total_ms, int64_t *la
 
 spiir_status spiir_bank_reset(spiir_bank *h, void *stream) {
     if (h == nullptr) return fail(SPIIR_E_INVAL, "bank is NULL");
+    spiir::Bank &bk = h->bk;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    h->bk.last_stream = s;
-    return zero_stream_state(h->bk, s);
+    if (bk.h_wait_flag != nullptr) {
+        // No launch still in flight may raise the flag after it is cleared.  The hand-off
+        // bookkeeping restarts as at creation: a wave that gave up on a wait may have
+        // left a flag behind the count the next launch expects.
+        SPIIR_HIP(hipStreamSynchronize(bk.last_stream));
+        SPIIR_HIP(hipStreamSynchronize(s));
+        SPIIR_TRY(zero_queue(bk, s));
+        SPIIR_HIP(hipStreamSynchronize(s));
+        __atomic_store_n(bk.h_wait_flag, 0u, __ATOMIC_RELEASE);
+    }
+    bk.last_stream = s;
+    return zero_stream_state(bk, s);
 }
 
 spiir_status spiir_bank_get_info(const spiir_bank *h, spiir_bank_info *info) {
@@ -612,6 +654,7 @@ spiir_status spiir_filter_chunk(spiir_bank *h, const float *x, int32_t n, float 
         }
         return SPIIR_OK;
     }
+    SPIIR_TRY(check_waits(bk));
     bk.last_stream = s;
     const bool timing = bk.timed < (int64_t)bk.ev_start.size();
     if (timing) SPIIR_HIP(hipEventRecord(bk.ev_start[bk.timed], s));
@@ -780,6 +823,7 @@ spiir_status spiir_forward(spiir_bank *h, const float *x, int32_t n, float *z, f
     spiir::Bank &bk = h->bk;
     SPIIR_TRY(check_diff_call(bk, x, n));
     if (z == nullptr) return fail(SPIIR_E_INVAL, "z is NULL");
+    SPIIR_TRY(check_waits(bk));
     hipStream_t s = static_cast<hipStream_t>(stream);
     bk.last_stream = s;
     SPIIR_TRY(zero_stream_state(bk, s));
@@ -798,6 +842,7 @@ spiir_status spiir_backward(spiir_bank *h, const float *x, int32_t n, const floa
         return fail(SPIIR_E_INVAL, "grad_z, ckpt, grad_a and grad_b must be non-NULL");
     if (spiir::backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl) > 160 * 1024)
         return fail(SPIIR_E_UNSUPPORTED, "ckpt_stride + max_delay too large for the adjoint window");
+    SPIIR_TRY(check_waits(bk));
     hipStream_t s = static_cast<hipStream_t>(stream);
     bk.last_stream = s;
     SPIIR_HIP(spiir::launch_backward(bk, x, n, reinterpret_cast<const float2 *>(grad_z),

@@ -116,6 +116,9 @@ struct Bank {
     ScanQueue *d_bqueue = nullptr;     // balanced schedule: launch epoch, finished waves, timeouts
     uint32_t *d_simd_tab = nullptr;    // balanced schedule: per-SIMD progress of co-resident waves
     float2 *d_bwd_part = nullptr;      // adjoint per-segment sums [D][bwd_max_seg][6][lanes]
+    uint32_t wait_spins = 1u << 22;    // bound of a state hand-off wait (polls)
+    uint32_t *h_wait_flag = nullptr;   // pinned host word: set by a wait that hit its bound
+    uint32_t *d_wait_flag = nullptr;   // its device alias
     std::vector<int32_t> h_slice_slots;  // slots of every slice (host copy, for planning)
     int32_t *d_order = nullptr;  // [D*n_slices]: det*n_slices + slice, largest slices first
     int32_t *d_slice_order = nullptr;  // [n_slices]: slices, largest first

@@ -329,8 +329,14 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
 // device-scope atomic accesses (coherent across XCDs, not held in the non-coherent
 // caches); the producer waits until those stores have completed before it moves
 // the flag (a device-scope atomic), and the consumer spins on the flag before it
-// loads the state.  The wait is bounded; a wait that hits the bound is counted.
-constexpr uint32_t kSpinLimit = 1u << 22;
+// loads the state.  The wait is bounded (`spins` polls of about 128 clocks); a wait
+// that hits the bound is counted in the bank's queue record and raises a flag in
+// host memory, which the library's next call reads (it then refuses to go on until
+// the stream is reset: the waiting wave went on with a stale state).
+struct WaitBound {
+    uint32_t spins;
+    uint32_t *host_flag;   // device alias of a word in pinned host memory
+};
 
 __device__ __forceinline__ float2 load_coherent(const float2 *p) {
     const uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
@@ -355,14 +361,15 @@ __device__ __forceinline__ void wait_memory() {
 // Wait until *flag has reached `target` (counts are compared modulo 2^32); lane 0
 // polls, the other lanes wait at the following wave-wide operations.
 __device__ __forceinline__ void wait_flag(const uint32_t *flag, uint32_t target, int lane,
-                                          uint32_t *error) {
+                                          uint32_t *error, WaitBound wb) {
     if (lane == 0) {
         uint32_t spins = 0;
         while ((int32_t)(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
                          target) < 0) {
             __builtin_amdgcn_s_sleep(2);
-            if (++spins == kSpinLimit) {
+            if (++spins >= wb.spins) {
                 __hip_atomic_fetch_add(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(wb.host_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 break;
             }
         }
@@ -479,7 +486,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) __attribute__((amdgpu_waves_per_
     int32_t n_splits, uint32_t *__restrict__ flags, ScanQueue *__restrict__ queue,
     int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
     int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, float2 *__restrict__ ckpt,
-    int32_t ckpt_stride, int32_t n_seg, uint32_t *__restrict__ simd_tab) {
+    int32_t ckpt_stride, int32_t n_seg, uint32_t *__restrict__ simd_tab, WaitBound wb) {
     extern __shared__ float smem[];
     float *win = smem;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -527,7 +534,7 @@ __global__ __launch_bounds__(kWave *kScanWaves) __attribute__((amdgpu_waves_per_
         }
         if (sg.phi0 > 0) {
             __builtin_amdgcn_s_setprio(0);   // a waiting wave yields the SIMD
-            wait_flag(fl + sg.flag, epoch + 1u, lane, &queue->error);
+            wait_flag(fl + sg.flag, epoch + 1u, lane, &queue->error, wb);
         }
 #pragma unroll
         for (int j = 0; j < MAXM; ++j) {
@@ -614,7 +621,7 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
     int32_t n_slices, int32_t n_det, int64_t lanes_total, const float *__restrict__ x, int32_t n,
     const float *__restrict__ hist, int32_t hist_len, float2 *__restrict__ partial,
     int32_t part_stride, int32_t tile, ScanQueue *__restrict__ queue,
-    uint32_t *__restrict__ flags) {
+    uint32_t *__restrict__ flags, WaitBound wb) {
     extern __shared__ float smem[];
     float *win = smem;
     const int lane = threadIdx.x;
@@ -665,7 +672,7 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
         // wait until the previous tile of this (detector, slice) has published its state
         uint32_t *flag = flags + (int64_t)det * n_slices + sidx;
         const uint32_t target = epoch + tau;
-        wait_flag(flag, target, lane, &queue->error);
+        wait_flag(flag, target, lane, &queue->error, wb);
         float2 *st = state + (int64_t)det * lanes_total;
 #pragma unroll
         for (int j = 0; j < MAXM; ++j) {
@@ -783,7 +790,8 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            scan_persistent_lds_bytes(bk.time_tile, bk.hist_len), s, bk.d_a, bk.d_b,
                            bk.d_delay, bk.d_state, bk.d_slices, bk.d_order, bk.n_slices, bk.n_det,
                            lanes, x, n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk,
-                           bk.time_tile, bk.d_queue, bk.d_flags);
+                           bk.time_tile, bk.d_queue, bk.d_flags,
+                           WaitBound{bk.wait_spins, bk.d_wait_flag});
     } else if (bk.balanced) {
         const dim3 grid((unsigned)((bk.balance_waves + kScanWaves - 1) / kScanWaves), bk.n_det);
         hipLaunchKernelGGL(scan_fp32_balanced_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
@@ -792,7 +800,7 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            bk.balance_waves, bk.n_splits, bk.d_split_flags, bk.d_bqueue, lanes, x,
                            n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk, ckpt,
                            bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride,
-                           bk.d_simd_tab);
+                           bk.d_simd_tab, WaitBound{bk.wait_spins, bk.d_wait_flag});
     } else {
         const int32_t tile = bk.scan_tile;
         const dim3 grid((bk.n_slices + kScanWaves - 1) / kScanWaves, bk.n_det);

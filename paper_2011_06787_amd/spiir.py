@@ -54,6 +54,7 @@ class Opts(ctypes.Structure):
         ("long_pole_abs_a", ctypes.c_double),
         ("ckpt_stride", ctypes.c_int32),
         ("balance_wgs", ctypes.c_int32),
+        ("wait_spins", ctypes.c_int32),
     ]
 
 
@@ -156,7 +157,7 @@ class SpiirBank:
                  max_delay: int = 0, peak_window: int = 0, mode: int = MODE_FP32_SCAN,
                  filters_per_lane: int = 0, time_tile: int = 0, block_len: int = 0,
                  long_pole_abs_a: float = 0.999, ckpt_stride: int = 0, balance_wgs: int = 0,
-                 stream=None):
+                 wait_spins: int = 0, stream=None):
         lib = load()
         self._offsets = np.ascontiguousarray(offsets, dtype=np.int32)
         self._a = np.ascontiguousarray(a, dtype=np.complex64)
@@ -166,7 +167,7 @@ class SpiirBank:
         o.n_detectors, o.max_chunk, o.max_delay = n_detectors, max_chunk, max_delay
         o.peak_window, o.mode, o.filters_per_lane = peak_window, mode, filters_per_lane
         o.time_tile, o.block_len, o.long_pole_abs_a = time_tile, block_len, long_pole_abs_a
-        o.ckpt_stride, o.balance_wgs = ckpt_stride, balance_wgs
+        o.ckpt_stride, o.balance_wgs, o.wait_spins = ckpt_stride, balance_wgs, wait_spins
         self.opts = o
         h = _P()
         st = lib.spiir_bank_create(int(self._offsets.shape[0] - 1),

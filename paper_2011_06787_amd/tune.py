@@ -7,8 +7,10 @@ persistent time-tiled work queue; split-bf16 block form: block length) on the ca
 packet length and detector count, and returns the fastest.  Candidates run on
 the real bank, or, for the block form whose operand set grows with the number
 of templates, on a seeded sample of templates (the time per filter-sample
-update is what is compared).  Every timing runs the library's own kernels;
-this module only chooses options.
+update is what is compared; every trial records how many templates it ran).  A
+sampled winner is timed again on the whole bank, when its operands fit in device
+memory, before it is returned; otherwise the fastest whole-bank trial is.  Every
+timing runs the library's own kernels; this module only chooses options.
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ class Trial:
     templates: int
     updates_per_s: float
     ms_per_packet: float
+    device_bytes: int = 0
 
 
 @dataclasses.dataclass
@@ -81,18 +84,21 @@ def _time_config(bank, x_packets, mode: int, opts: Dict[str, int], reps: int) ->
         stop.record()
         torch.cuda.synchronize()
         ms = start.elapsed_time(stop) / reps
+        dev_bytes = int(sb.info.device_bytes)
     upd = int(bank.offsets[-1]) * D * n
-    return Trial(mode, dict(opts), bank.n_templates, upd / (ms * 1e-3), ms)
+    return Trial(mode, dict(opts), bank.n_templates, upd / (ms * 1e-3), ms, dev_bytes)
 
 
 def autotune(bank, x_packets: Sequence, *, scan_candidates: Optional[List[dict]] = None,
-             block_candidates: Optional[List[dict]] = None, block_sample_templates: int = 256,
+             block_candidates: Optional[List[dict]] = None, block_sample_templates: int = 1024,
              reps: int = 10, seed: int = 0):
     """Return (best_trial, all_trials).
 
     ``x_packets``: a few cuda float32 [D][n] packets of the stream to tune for.
     Block-form candidates need n to be a multiple of their block length; they are
-    timed on ``block_sample_templates`` seeded templates (all when fewer).
+    timed on ``block_sample_templates`` seeded templates (all when fewer; 1024 templates
+    of a few hundred filters fill every compute unit).  The returned trial always ran
+    on the whole bank.
     """
     scan_candidates = DEFAULT_SCAN if scan_candidates is None else scan_candidates
     block_candidates = DEFAULT_BLOCK if block_candidates is None else block_candidates
@@ -113,4 +119,13 @@ def autotune(bank, x_packets: Sequence, *, scan_candidates: Optional[List[dict]]
                 continue
             trials.append(_time_config(sub, x_packets, spiir.MODE_BF16_BLOCK, opts, reps))
     best = max(trials, key=lambda t: t.updates_per_s)
+    if best.templates < bank.n_templates:
+        # a sampled winner: time it on the whole bank if its operands fit, else fall back
+        import torch
+        free, _ = torch.cuda.mem_get_info()
+        need = best.device_bytes * bank.n_templates / max(best.templates, 1)
+        if need < 0.8 * free:
+            trials.append(_time_config(bank, x_packets, best.mode, best.opts, reps))
+        whole = [t for t in trials if t.templates == bank.n_templates]
+        best = max(whole, key=lambda t: t.updates_per_s)
     return best, trials

@@ -243,3 +243,25 @@ def test_realistic_bank_full_size_sampled(gpu):
     for c in range(8):
         check_peaks(pk[c][:, pick], am[c][:, pick], z[:, pick, c * 2048:(c + 1) * 2048],
                     z_ref[..., c * 2048:(c + 1) * 2048], 2048)
+
+
+def test_wait_timeout_is_reported_until_reset(gpu):
+    """A state hand-off wait that hits its bound, forced from the host with a bound of one
+    poll on the persistent scan (its tile-1 items start while the tile-0 items they need
+    are still running): every wave still finishes, the bank counts the timeouts, the next
+    filter_chunk returns SPIIR_E_STATE without enqueueing anything, and a reset clears
+    the count and the status."""
+    import torch
+    w = synth.realistic(n_templates=64, seconds=2)
+    x = torch.from_numpy(w.input()).cuda()
+    with gpu.SpiirBank.from_bank(w.bank, max_chunk=2048, time_tile=256, wait_spins=1) as sb:
+        sb.filter_chunk(x[:, :2048].contiguous(), want_peaks=False)
+        torch.cuda.synchronize()
+        assert sb.refresh_info().scan_wait_timeouts > 0
+        with pytest.raises(gpu.SpiirError) as exc:
+            sb.filter_chunk(x[:, 2048:].contiguous(), want_peaks=False)
+        assert exc.value.status == gpu.SPIIR_E_STATE
+        sb.reset()
+        assert sb.refresh_info().scan_wait_timeouts == 0
+        sb.filter_chunk(x[:, 2048:].contiguous(), want_peaks=False)   # accepted again
+        torch.cuda.synchronize()

@@ -79,3 +79,14 @@ def test_triggers_end_to_end_on_noise(gpu):
     assert np.all(idx[d, t, k] // 2048 == k)
     assert np.allclose(snr[d, t, k], vals, rtol=1e-5)
     assert np.all(snr[d, t, k] > 4.0)
+
+
+def test_triggers_threshold_is_strict(gpu):
+    # samples at exactly threshold^2 are not candidates, one just above is (Sec. II.C.1:
+    # SNRs over the threshold); expected values written out by hand
+    import torch
+    from helpers import threshold_fixture
+    z, w, window, exp_idx, exp_snr = threshold_fixture()
+    snr, idx = gpu.triggers(torch.from_numpy(z).cuda(), torch.from_numpy(w).cuda(), 4.0, window)
+    assert np.array_equal(idx.cpu().numpy(), exp_idx)
+    assert np.array_equal(snr.cpu().numpy(), exp_snr)

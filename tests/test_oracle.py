@@ -18,6 +18,7 @@ import scipy.signal
 
 import oracle
 import synth
+from helpers import threshold_fixture
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -451,6 +452,14 @@ def test_triggers_brute_force_with_ties_and_threshold():
     assert idx[1, 1, 1] == 70
     # every trigger is above threshold and at most one per (template, window)
     assert np.all(snr[idx >= 0] > 4.0) and np.all(snr[idx < 0] == 0)
+
+
+def test_triggers_threshold_is_strict():
+    z, w, window, exp_idx, exp_snr = threshold_fixture()
+    assert np.float32(np.float32(4.0) * np.float32(4.0)) == np.float32(16.0)
+    snr, idx = oracle.triggers(z, w, 4.0, window)
+    assert np.array_equal(idx, exp_idx)
+    assert np.array_equal(snr, exp_snr)
 
 
 # ---- signal-consistency statistic (Section II.C.1) ----
