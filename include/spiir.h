@@ -205,6 +205,25 @@ spiir_status spiir_triggers(const float *z, int32_t n_det, int32_t n_templates, 
                             float *snr, int32_t *index, void *stream);
 
 /*
+ * spiir_triggers without the `work` argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as spiir_triggers; the key slots
+ * live in a workspace the library keeps on every device it runs on (8 MiB, held until
+ * the process ends), so the call allocates nothing.
+ *   n_det * n_templates * ceil(n / window) must be <= 1048576, else SPIIR_E_INVAL
+ *   (nothing enqueued).
+ *   stream must belong to the calling thread's current device.
+ * The first call on a device looks up that device's workspace address (not a stream
+ * operation).  Every call on one device shares its workspace: calls that overlap in
+ * time on one device (other streams, other host threads) race and give undefined
+ * results; calls on one stream are ordered and safe.  The slots are cleared by a
+ * kernel at the start of every call.
+ */
+spiir_status spiir_triggers_noalloc(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                                    const float *weight, float threshold, int32_t window,
+                                    float *snr, int32_t *index, void *stream);
+
+/*
  * ---- Signal-consistency statistic (Section II.C.1) ----
  * The correlation of each template with itself,
  *   R_t[j] = sum_m u_t[m+j] conj(u_t[m]),  j = 0..nj   (R_t[-j] = conj(R_t[j])),

@@ -722,6 +722,28 @@ spiir_status spiir_triggers(const float *z, int32_t n_det, int32_t n_templates, 
     return SPIIR_OK;
 }
 
+spiir_status spiir_triggers_noalloc(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                                    const float *weight, float threshold, int32_t window,
+                                    float *snr, int32_t *index, void *stream) {
+    if (n_det < 0 || n_templates < 0 || n < 0) return fail(SPIIR_E_INVAL, "sizes must be >= 0");
+    if (window < 1) return fail(SPIIR_E_INVAL, "window must be >= 1");
+    if (!std::isfinite(threshold) || threshold < 0.0f)
+        return fail(SPIIR_E_INVAL, "threshold must be finite and >= 0");
+    if ((int64_t)n_det * n_templates * n == 0) return SPIIR_OK;
+    const int64_t slots = (int64_t)n_det * n_templates * (((int64_t)n + window - 1) / window);
+    if (slots > spiir::kTriggerScratchSlots)
+        return fail(SPIIR_E_INVAL, "n_det * n_templates * ceil(n / window) = " +
+                                       std::to_string(slots) + " exceeds the " +
+                                       std::to_string(spiir::kTriggerScratchSlots) +
+                                       " slots of the library's trigger workspace");
+    if (z == nullptr || weight == nullptr || snr == nullptr || index == nullptr)
+        return fail(SPIIR_E_INVAL, "z, weight, snr and index must be non-NULL");
+    SPIIR_HIP(spiir::launch_triggers_noalloc(reinterpret_cast<const float2 *>(z), n_det,
+                                             n_templates, n, weight, threshold, window, snr, index,
+                                             static_cast<hipStream_t>(stream)));
+    return SPIIR_OK;
+}
+
 spiir_status spiir_bank_autocorr(const spiir_bank *h, int32_t nj, double *R, void *stream) {
     if (h == nullptr || R == nullptr) return fail(SPIIR_E_INVAL, "bank or R is NULL");
     if (nj < 1 || nj > 4096) return fail(SPIIR_E_INVAL, "nj must be in [1, 4096]");

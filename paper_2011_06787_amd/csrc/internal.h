@@ -175,6 +175,11 @@ hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t s);
 hipError_t launch_triggers(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
                            const float *weight, float threshold, int32_t window,
                            unsigned long long *work, float *snr, int32_t *index, hipStream_t s);
+// Key slots (64-bit) of the workspace spiir_triggers_noalloc keeps on every device.
+constexpr int64_t kTriggerScratchSlots = int64_t(1) << 20;
+hipError_t launch_triggers_noalloc(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
+                                   const float *weight, float threshold, int32_t window,
+                                   float *snr, int32_t *index, hipStream_t s);
 hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *z, hipStream_t s);
 hipError_t launch_autocorr(int32_t n_templates, const int32_t *offsets, const float2 *a,
                            const float2 *b, const int32_t *d, int32_t nj, double2 *R, hipStream_t s);

@@ -9,6 +9,7 @@
 // block-wide arg-max reduction uses wave shuffles and one LDS exchange.
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "internal.h"
 
@@ -318,6 +319,52 @@ hipError_t launch_triggers(const float2 *z, int32_t n_det, int32_t n_templates, 
     hipLaunchKernelGGL(trigger_decode_kernel, dim3((unsigned)blocks), dim3(256), 0, s, work, count,
                        snr, index);
     return hipGetLastError();
+}
+
+namespace {
+
+// Key slots of spiir_triggers_noalloc: a library-owned workspace for callers that
+// cannot allocate.  Every GPU holds its own copy until the process ends; every call
+// on one GPU shares it.  In host code the name is a stand-in for the device copy, so
+// kernels get the address looked up per device below, never the name itself.
+static __device__ __align__(256) unsigned long long scratch[kTriggerScratchSlots];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch`, looked up once per device.
+hipError_t scratch_address(unsigned long long **out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<unsigned long long *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_triggers_noalloc(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
+                                   const float *weight, float threshold, int32_t window,
+                                   float *snr, int32_t *index, hipStream_t s) {
+    const int64_t count = (int64_t)n_det * n_templates * ((n + window - 1) / window);
+    if (count > kTriggerScratchSlots) return hipErrorInvalidValue;   // checked by the caller
+    unsigned long long *work = nullptr;
+    const hipError_t e = scratch_address(&work);
+    if (e != hipSuccess) return e;
+    // the same kernels as launch_triggers; the slots are cleared there by a kernel
+    return launch_triggers(z, n_det, n_templates, n, weight, threshold, window, work, snr, index,
+                           s);
 }
 
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t s) {

@@ -31,7 +31,7 @@ EXPORTS = (
     "spiir_bank_get_info", "spiir_filter_chunk", "spiir_peaks", "spiir_last_error",
     "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count", "spiir_forward",
     "spiir_backward", "spiir_bank_set_coeffs", "spiir_bank_noise_power", "spiir_triggers",
-    "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent",
+    "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent", "spiir_triggers_noalloc",
 )
 
 
@@ -103,6 +103,8 @@ def load():
     lib.spiir_bank_noise_power.argtypes = [_P, _P]
     lib.spiir_triggers.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                    ctypes.c_float, ctypes.c_int32, _P, _P, _P, _P]
+    lib.spiir_triggers_noalloc.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                           ctypes.c_float, ctypes.c_int32, _P, _P, _P]
     lib.spiir_bank_autocorr.argtypes = [_P, ctypes.c_int32, _P, _P]
     lib.spiir_xi2.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                               _P, ctypes.c_int32, _P, _P]
@@ -115,7 +117,8 @@ def load():
                  "spiir_bank_get_info", "spiir_filter_chunk", "spiir_peaks",
                  "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count",
                  "spiir_forward", "spiir_backward", "spiir_bank_set_coeffs",
-                 "spiir_bank_noise_power", "spiir_triggers"):
+                 "spiir_bank_noise_power", "spiir_triggers", "spiir_triggers_noalloc",
+                 "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -392,6 +395,29 @@ def triggers(z, weight, threshold: float = 4.0, window: int = 2048, work=None, s
     _check("spiir_triggers", load().spiir_triggers(z.data_ptr(), D, T, n, weight.data_ptr(),
                                                    float(threshold), int(window), work.data_ptr(),
                                                    snr.data_ptr(), idx.data_ptr(), _stream_ptr(stream)))
+    return snr, idx
+
+
+def triggers_noalloc(z, weight, threshold: float = 4.0, window: int = 2048, out=None,
+                     stream=None):
+    """``triggers`` through the entry point that allocates nothing: the key slots are
+    the library's per-device workspace.  ``out`` = (snr, index) preallocated
+    [D][T][W] tensors, else they are allocated here (by torch, outside the call)."""
+    import torch
+    assert z.is_cuda and z.dtype == torch.complex64 and z.is_contiguous() and z.dim() == 3
+    D, T, n = (int(v) for v in z.shape)
+    W = (n + window - 1) // window
+    if out is None:
+        out = (torch.empty((D, T, W), dtype=torch.float32, device=z.device),
+               torch.empty((D, T, W), dtype=torch.int32, device=z.device))
+    snr, idx = out
+    assert snr.dtype == torch.float32 and idx.dtype == torch.int32
+    assert snr.is_contiguous() and idx.is_contiguous() and snr.numel() >= D * T * W
+    assert idx.numel() >= D * T * W
+    _check("spiir_triggers_noalloc",
+           load().spiir_triggers_noalloc(z.data_ptr(), D, T, n, weight.data_ptr(), float(threshold),
+                                         int(window), snr.data_ptr(), idx.data_ptr(),
+                                         _stream_ptr(stream)))
     return snr, idx
 
 

@@ -117,3 +117,17 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(spiir, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="libspiir.so not found"):
         spiir.load()
+
+
+def test_triggers_noalloc_rejects_oversize_and_bad_arguments_without_gpu():
+    # the workspace holds 2^20 key slots: one more is refused before anything is enqueued
+    lib = spiir.load()
+    f = lib.spiir_triggers_noalloc
+    dummy = ctypes.c_void_p(16)   # never dereferenced: every case fails on the host
+    assert f(dummy, 2, 1 << 19, 2049, dummy, 4.0, 2048, dummy, dummy, None) == spiir.SPIIR_E_INVAL
+    assert "workspace" in spiir.last_error()
+    assert f(dummy, 1, (1 << 20) + 1, 16, dummy, 4.0, 16, dummy, dummy, None) == spiir.SPIIR_E_INVAL
+    assert f(dummy, 1, 2, 100, dummy, 4.0, 0, dummy, dummy, None) == spiir.SPIIR_E_INVAL   # window 0
+    assert f(dummy, 1, 2, 100, dummy, -1.0, 8, dummy, dummy, None) == spiir.SPIIR_E_INVAL  # threshold
+    assert f(None, 1, 2, 100, None, 4.0, 8, None, None, None) == spiir.SPIIR_E_INVAL      # NULLs
+    assert f(None, 0, 2, 100, None, 4.0, 8, None, None, None) == spiir.SPIIR_OK           # empty
