@@ -120,3 +120,44 @@ def test_fitting_raises_the_overlap(gpu):
     print(f"overlap {h[0]:.4f} -> {h[-1]:.4f}")
     assert h[-1] > h[0]
     assert float(res["a"].abs().max()) < 1.0
+
+
+def test_projection_through_the_adjoint_matches_direct_projection(gpu):
+    """b from spiir_backward (impulse input, grad_z = target) over the closed-form norm
+    equals the projection on an explicitly built FP64 basis."""
+    import torch
+    from paper_2011_06787_amd import fit
+    tg = synth.chirp_targets(3, 4, 2048)
+    off, a, d = fit.design(tg, 64)
+    with gpu.SpiirBank(off, a, np.ones_like(a), d, max_chunk=2048, ckpt_stride=512) as sb:
+        b = fit.project_b(sb, torch.from_numpy(a).cuda(), d, torch.from_numpy(tg).cuda())
+    b = b.cpu().numpy()
+    m = np.arange(2048)
+    for t in range(4):
+        sl = slice(t * 64, (t + 1) * 64)
+        k = m[None, :] - d[sl][:, None]
+        B = np.where(k >= 0, a[sl].astype(np.complex128)[:, None] ** np.maximum(k, 0), 0)
+        ref = (B.conj() @ tg[t].astype(np.complex128)) / np.sum(np.abs(B) ** 2, axis=1)
+        assert np.linalg.norm(b[sl] - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+def test_fit_reaches_the_target_overlap_on_the_differentiation_workload(gpu):
+    """All 256 chirp targets (chirp mass uniform in [1, 5], 4 s at 2048 Hz) with 512
+    filters each: design, projection and 200 Adam steps through the adjoint.  The
+    fitted coefficients, re-scored by the FP64 oracle, overlap every target above 0.97
+    (the paper's design reaches > 97% for most templates with <= 350 filters, Sec. III,
+    and over 99% in Sec. II.B.1), and the fit raises the design's overlap."""
+    from paper_2011_06787_amd import fit
+    tg = synth.chirp_targets(0, 256, 8192)
+    res = fit.fit_targets(tg, n_filters=512, steps=200)
+    bank = synth.Bank(res["offsets"], res["a"].astype(np.complex64),
+                      res["b"].astype(np.complex64), res["delay"])
+    ov, _, _ = oracle.overlap_grad(bank, tg)
+    design = synth.Bank(res["offsets"], res["a_design"], res["b_design"], res["delay"])
+    ov0, _, _ = oracle.overlap_grad(design, tg)
+    print(f"overlap design {ov0.mean():.5f} (min {ov0.min():.5f}) -> fit {ov.mean():.5f} "
+          f"(min {ov.min():.5f}); {res['seconds']}")
+    assert ov.min() >= 0.97 and ov.mean() >= 0.99
+    assert ov.mean() > ov0.mean()
+    assert abs(ov.mean() - res["overlap_history"][-1]) < 1e-3
+    assert float(np.abs(res["a"]).max()) < 1.0
