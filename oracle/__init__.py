@@ -299,6 +299,47 @@ def xi2(z: np.ndarray, index: np.ndarray, R: np.ndarray, nj: int) -> np.ndarray:
     return out
 
 
+def xi2_network(z: np.ndarray, index: np.ndarray, pix: np.ndarray, tau: np.ndarray,
+                R: np.ndarray, nj: int):
+    """xi^2 of every detector at a coherent candidate and their mean xi^2_C (Section
+    II.C.1: xi^2_C = (1/N_d) sum_I xi_I^2).
+
+    For the candidate of detector I, template t, window w at sample c = index[I, t, w]
+    with sky direction p = pix[I, t, w] (the coherent stage's best direction), detector J
+    is read at its arrival time in that direction, s_J = c + tau[p, J] - tau[p, I], and
+      xi_J^2 = sum_{j=-nj..nj} |v_J[s_J+j] - v_J[s_J] A[j]|^2 / sum_{j=-nj..nj} (2 - 2|A[j]|^2)
+    with A[j] = R_t[j] / R_t[0] (A[-j] = conj(A[j])) and v_J = z[J, t] * sqrt(2 / R_t[0]).
+    Returns (xi2_det float64 [D][T][W][D] (last axis J), xi2_c float64 [D][T][W]); NaN
+    where there is no candidate (c < 0 or p < 0) or some s_J +- nj leaves [0, n).
+    Plain FP64 loops.
+    """
+    z = np.asarray(z, dtype=np.complex128)
+    D, T, n = z.shape
+    W = index.shape[2]
+    per = np.full((D, T, W, D), np.nan)
+    mean = np.full((D, T, W), np.nan)
+    for t in range(T):
+        r0 = R[t, 0].real
+        A = np.concatenate([np.conj(R[t, nj:0:-1]), R[t, :nj + 1]]) / r0     # j = -nj..nj
+        den = np.sum(2.0 - 2.0 * np.abs(A) ** 2)
+        scale = np.sqrt(2.0 / r0)
+        for I in range(D):
+            for w in range(W):
+                c, p = int(index[I, t, w]), int(pix[I, t, w])
+                if c < 0 or p < 0:
+                    continue
+                s = [c + int(tau[p, J]) - int(tau[p, I]) for J in range(D)]
+                if min(s) - nj < 0 or max(s) + nj >= n:
+                    continue
+                vals = []
+                for J in range(D):
+                    v = z[J, t, s[J] - nj:s[J] + nj + 1] * scale
+                    vals.append(np.sum(np.abs(v - v[nj] * A) ** 2) / den)
+                per[I, t, w, :] = vals
+                mean[I, t, w] = sum(vals) / D
+    return per, mean
+
+
 def coherent_map(z: np.ndarray, index: np.ndarray, U: np.ndarray, tau: np.ndarray,
                  shifts: np.ndarray):
     """Coherent and null SNR^2 of every candidate at every sky direction and time shift

@@ -523,6 +523,99 @@ def test_xi2_has_mean_one_on_white_noise():
     assert abs(m - 1.0) < 0.02, m     # mean 1.001, std of the mean 0.003 at this seed
 
 
+def _acf(R, t, nj):
+    return np.concatenate([np.conj(R[t, nj:0:-1]), R[t, :nj + 1]]) / R[t, 0].real
+
+
+def test_xi2_network_reads_every_detector_at_its_arrival_time():
+    # Each detector holds the exact scaled autocorrelation centred where the candidate's
+    # direction puts it, s_J = c + tau[p, J] - tau[p, I]: every xi_J^2 is 0 there, so
+    # xi^2_C = 0.  The direction with the offsets reversed reads the wrong samples
+    # (xi^2_C > 0.1).  An offset e at one lag of one detector gives that detector
+    # |e|^2 (2 / R0) / sum(2 - 2|A|^2) and the mean a third of it.
+    bank = small_bank(56, [7, 9], max_delay=60, tau=(0.002, 0.02))
+    nj, n, c, I = 40, 600, 300, 1
+    R = oracle.autocorr(bank, nj)
+    tau = np.array([[5, -3, 12], [-5, 3, -12]], dtype=np.int32)
+    z = np.zeros((3, 2, n), dtype=np.complex128)
+    amp = [1.0 + 2.0j, -0.5 + 0.3j, 2.5 - 1.0j]
+    for t in range(2):
+        for J in range(3):
+            s = c + tau[0, J] - tau[0, I]
+            z[J, t, s - nj:s + nj + 1] = amp[J] * _acf(R, t, nj)
+    e = 0.4 - 0.9j
+    s2 = c + tau[0, 2] - tau[0, I]
+    z[2, 1, s2 - 11] += e
+    idx = np.full((3, 2, 1), -1, dtype=np.int32)
+    idx[I, :, 0] = c
+    pix = np.zeros((3, 2, 1), dtype=np.int32)
+    per, mean = oracle.xi2_network(z, idx, pix, tau, R, nj)
+    assert np.all(np.abs(per[I, 0, 0]) < 1e-24) and abs(mean[I, 0, 0]) < 1e-24
+    A1 = _acf(R, 1, nj)
+    expect = abs(e) ** 2 * (2.0 / R[1, 0].real) / np.sum(2 - 2 * np.abs(A1) ** 2)
+    assert abs(per[I, 1, 0, 2] - expect) < 1e-12 * expect
+    assert abs(per[I, 1, 0, 0]) < 1e-24 and abs(per[I, 1, 0, 1]) < 1e-24
+    assert abs(mean[I, 1, 0] - expect / 3.0) < 1e-12 * expect
+    assert np.all(np.isnan(mean[[0, 2]])) and np.all(np.isnan(per[[0, 2]]))   # no candidate
+    pix[:] = 1
+    _, wrong = oracle.xi2_network(z, idx, pix, tau, R, nj)
+    assert np.all(wrong[I, :, 0] > 0.1)
+
+
+def test_xi2_network_single_detector_is_xi2():
+    bank = small_bank(57, [10, 4, 30], max_delay=200, tau=(0.002, 0.05))
+    nj, n = 50, 3000
+    x = np.random.default_rng(58).standard_normal((1, n))
+    z = oracle.filter(bank, x)
+    R = oracle.autocorr(bank, nj)
+    idx = np.random.default_rng(59).integers(-1, n, size=(1, 3, 6)).astype(np.int32)
+    idx[0, 0, :2] = [10, n - 5]                    # too close to the ends: NaN
+    tau = np.array([[17], [-4]], dtype=np.int32)   # one detector: every offset cancels
+    pix = (np.arange(18).reshape(1, 3, 6) % 2).astype(np.int32)
+    per, mean = oracle.xi2_network(z, idx, pix, tau, R, nj)
+    ref = oracle.xi2(z, idx, R, nj)
+    assert np.array_equal(np.isnan(mean), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert ok.sum() >= 8
+    assert np.array_equal(mean[ok], ref[ok]) and np.array_equal(per[..., 0][ok], ref[ok])
+
+
+def test_xi2_network_has_mean_one_on_white_noise():
+    # three detectors of independent unit white noise, candidates at spaced samples with
+    # random directions: the detector average keeps the reduced chi-square's mean 1
+    bank = small_bank(60, [8, 8], max_delay=150, tau=(0.002, 0.01))
+    nj, n, D = 60, 120_000, 3
+    x = np.random.default_rng(61).standard_normal((D, n))
+    z = oracle.filter(bank, x)
+    R = oracle.autocorr(bank, nj)
+    rng = np.random.default_rng(62)
+    tau = rng.integers(-44, 45, size=(16, D)).astype(np.int32)
+    pos = np.arange(2000, n - 200, 2 * nj + 101)
+    idx = np.broadcast_to(pos, (D, bank.n_templates, len(pos))).astype(np.int32).copy()
+    pix = rng.integers(0, 16, size=idx.shape).astype(np.int32)
+    per, mean = oracle.xi2_network(z, idx, pix, tau, R, nj)
+    assert not np.isnan(mean).any()
+    m = float(np.mean(mean))
+    assert abs(m - 1.0) < 0.03, m
+    assert np.allclose(mean, per.mean(axis=-1), rtol=1e-12)
+
+
+def test_xi2_network_undefined_cases():
+    bank = small_bank(63, [5], max_delay=20, tau=(0.002, 0.01))
+    nj, n = 10, 200
+    R = oracle.autocorr(bank, nj)
+    z = np.ones((2, 1, n), dtype=np.complex128)
+    tau = np.array([[0, 30]], dtype=np.int32)
+    idx = np.array([[[100, 165, -1, 100]], [[50, 20, 100, 100]]], dtype=np.int32)
+    pix = np.array([[[0, 0, 0, -1]], [[0, 0, 0, 0]]], dtype=np.int32)
+    per, mean = oracle.xi2_network(z, idx, pix, tau, R, nj)
+    # det 0: c=100 fine (s_1 = 130); c=165 puts detector 1 at 195 (+10 leaves the series);
+    # no candidate; no direction.  det 1: c=50 puts detector 0 at 20 (fine), c=20 at -10
+    ok = ~np.isnan(mean)
+    assert ok.tolist() == [[[True, False, False, False]], [[True, False, True, True]]]
+    assert np.array_equal(np.isnan(per).all(axis=-1), ~ok)
+
+
 # ---- coherent search (Section II.C.1) ----
 
 def _rand_z(rng, D, T, n, scale=1.0):
