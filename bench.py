@@ -599,6 +599,27 @@ def coherent_run(args, dev):
         out["checked"] = int(ok.sum())
         out["rel_err_max"] = float(np.max(np.abs(g2[ok] - best[ok]) / best[ok])) if ok.any() else None
         out["direction_agreement"] = float(np.mean(gp[ok] == opix[ok])) if ok.any() else None
+        # detector-average xi^2_C at the foreground directions (nj = 175)
+        nj = 175
+        R = sb.autocorr(nj)
+        pix0 = fp[..., 0].contiguous()
+        spiir.xi2_network(z, idx, pix0, args_fg[1], R, nj)
+        torch.cuda.synchronize()
+        e[0].record()
+        xper, xc = spiir.xi2_network(z, idx, pix0, args_fg[1], R, nj)
+        e[1].record()
+        torch.cuda.synchronize()
+        xc_h = xc.cpu().numpy()
+        xok = ~np.isnan(xc_h)
+        _, xc_ref = oracle.xi2_network(z_ref, idx_sel, gp[..., 0], fg.tau,
+                                       oracle.autocorr(sub, nj), nj)
+        xsel = xc_h[:, pick]
+        xr_ok = ~np.isnan(xc_ref)
+        out["xi2_c"] = {"nj": nj, "evaluated": int(xok.sum()), "us": e[0].elapsed_time(e[1]) * 1e3,
+                        "mean": float(xc_h[xok].mean()) if xok.any() else None,
+                        "checked": int(xr_ok.sum()),
+                        "rel_err_max": float(np.max(np.abs(xsel[xr_ok] - xc_ref[xr_ok]) / xc_ref[xr_ok]))
+                        if xr_ok.any() else None}
     log(f"coherent: {out['candidates']} candidates, foreground {out['foreground_ms']:.3f} ms, "
         f"background {out['background_ms']:.3f} ms")
     return out

@@ -255,6 +255,28 @@ spiir_status spiir_xi2(const float *z, int32_t n_det, int32_t n_templates, int32
                        void *stream);
 
 /*
+ * The detector average xi^2_C = (1/N_d) sum_J xi_J^2 of Section II.C.1 at coherent
+ * candidates.  For the candidate of detector I, template t, window w at sample
+ * c = index[I][t][w] with sky direction p = pix[I][t][w] (the coherent stage's best
+ * direction, e.g. spiir_coherent's pix with one, unshifted, time shift), detector J is
+ * read at its arrival time in that direction, s_J = c + tau[p][J] - tau[p][I], and xi_J^2
+ * is spiir_xi2's statistic of series z[J][t] at s_J (FP64 sums).
+ *   z        device complex64 [n_det][n_templates][n], 1 <= n_det <= 8
+ *   index    device int32 [n_det][n_templates][n_win], -1 = no candidate
+ *   pix      device int32 [n_det][n_templates][n_win], -1 = no direction
+ *   tau      device int32 [n_pix][n_det]: the arrival-time offsets spiir_coherent used
+ *   R        device double [n_templates][nj+1][2] from spiir_bank_autocorr with the same nj
+ *   xi2_det  device float32 [n_det][n_templates][n_win][n_det] (last index J), or NULL
+ *   xi2_c    device float32 [n_det][n_templates][n_win]: the mean over J, in detector order
+ * NaN where there is no candidate, p is outside [0, n_pix), or some s_J - nj < 0 or
+ * s_J + nj >= n.
+ */
+spiir_status spiir_xi2_network(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                               const int32_t *index, const int32_t *pix, int32_t n_win,
+                               const int32_t *tau, int32_t n_pix, const double *R, int32_t nj,
+                               float *xi2_det, float *xi2_c, void *stream);
+
+/*
  * ---- Coherent search (Section II.C.1, Eq. llr_form; null statistic of the appendix) ----
  * For every candidate (detector I, template t, window w) at sample c = index[I][t][w],
  * every time shift k and every sky direction p, detector J contributes

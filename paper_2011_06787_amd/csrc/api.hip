@@ -800,6 +800,25 @@ spiir_status spiir_xi2(const float *z, int32_t n_det, int32_t n_templates, int32
     return SPIIR_OK;
 }
 
+spiir_status spiir_xi2_network(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
+                               const int32_t *index, const int32_t *pix, int32_t n_win,
+                               const int32_t *tau, int32_t n_pix, const double *R, int32_t nj,
+                               float *xi2_det, float *xi2_c, void *stream) {
+    if (n_det < 1 || n_det > 8) return fail(SPIIR_E_INVAL, "n_det must be in [1, 8]");
+    if (n_templates < 0 || n < 0 || n_win < 0 || n_pix < 0)
+        return fail(SPIIR_E_INVAL, "sizes must be >= 0");
+    if (nj < 1 || nj > 4096) return fail(SPIIR_E_INVAL, "nj must be in [1, 4096]");
+    if ((int64_t)n_templates * n_win == 0) return SPIIR_OK;
+    if (z == nullptr || index == nullptr || pix == nullptr || R == nullptr || xi2_c == nullptr ||
+        (n_pix > 0 && tau == nullptr))
+        return fail(SPIIR_E_INVAL, "z, index, pix, tau, R and xi2_c must be non-NULL");
+    SPIIR_HIP(spiir::launch_xi2_network(reinterpret_cast<const float2 *>(z), n_det, n_templates, n,
+                                        index, pix, n_win, tau, n_pix,
+                                        reinterpret_cast<const double2 *>(R), nj, xi2_det, xi2_c,
+                                        static_cast<hipStream_t>(stream)));
+    return SPIIR_OK;
+}
+
 spiir_status spiir_coherent(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
                             const int32_t *index, int32_t n_win, const float *U, const int32_t *tau,
                             int32_t n_pix, const int32_t *shifts, int32_t n_shift, float *snr2,

@@ -190,6 +190,10 @@ hipError_t launch_coherent(const float2 *z, int32_t n_det, int32_t n_templates, 
 hipError_t launch_xi2(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
                       const int32_t *index, int32_t n_win, const double2 *R, int32_t nj, float *xi2,
                       hipStream_t s);
+hipError_t launch_xi2_network(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
+                              const int32_t *index, const int32_t *pix, int32_t n_win,
+                              const int32_t *tau, int32_t n_pix, const double2 *R, int32_t nj,
+                              float *xi2_det, float *xi2_c, hipStream_t s);
 int32_t block_state_xwin(const Bank &bk);
 size_t block_state_lds_bytes(const Bank &bk);
 hipError_t prepare_block_bf16(const Bank &bk);

@@ -116,21 +116,11 @@ __global__ __launch_bounds__(kAcThreads) void autocorr_kernel(const int32_t *__r
     }
 }
 
-__global__ __launch_bounds__(kWave) void xi2_kernel(const float2 *__restrict__ z, int32_t n_templates,
-                                                    int32_t n, const int32_t *__restrict__ index,
-                                                    int32_t n_win, const double2 *__restrict__ R,
-                                                    int32_t nj, float *__restrict__ xi2) {
-    const int64_t cand = blockIdx.x;   // (row, window)
-    const int64_t row = cand / n_win;
-    const int t = (int)(row % n_templates);
-    const int lane = threadIdx.x;
-    const int c = index[cand];
-    if (c < 0 || c - nj < 0 || c + nj >= n) {
-        if (lane == 0) xi2[cand] = __builtin_nanf("");
-        return;
-    }
-    const float2 *zr = z + row * (int64_t)n;
-    const double2 *Rt = R + (int64_t)t * (nj + 1);
+// xi^2 of the series zr at candidate sample c (c - nj >= 0, c + nj < n checked by the
+// caller), returned in every lane of the wave: one wave, lags strided over the lanes,
+// FP64 sums reduced with shuffles.
+__device__ __forceinline__ double xi2_wave(const float2 *__restrict__ zr, int c,
+                                           const double2 *__restrict__ Rt, int nj, int lane) {
     const double r0 = Rt[0].x;
     const double zcr = zr[c].x, zci = zr[c].y;
     double num = 0.0, den = 0.0;
@@ -146,7 +136,72 @@ __global__ __launch_bounds__(kWave) void xi2_kernel(const float2 *__restrict__ z
         num += __shfl_xor(num, off);
         den += __shfl_xor(den, off);
     }
-    if (lane == 0) xi2[cand] = (float)(num * (2.0 / r0) / den);
+    return num * (2.0 / r0) / den;
+}
+
+__global__ __launch_bounds__(kWave) void xi2_kernel(const float2 *__restrict__ z, int32_t n_templates,
+                                                    int32_t n, const int32_t *__restrict__ index,
+                                                    int32_t n_win, const double2 *__restrict__ R,
+                                                    int32_t nj, float *__restrict__ xi2) {
+    const int64_t cand = blockIdx.x;   // (row, window)
+    const int64_t row = cand / n_win;
+    const int t = (int)(row % n_templates);
+    const int lane = threadIdx.x;
+    const int c = index[cand];
+    if (c < 0 || c - nj < 0 || c + nj >= n) {
+        if (lane == 0) xi2[cand] = __builtin_nanf("");
+        return;
+    }
+    const double v = xi2_wave(z + row * (int64_t)n, c, R + (int64_t)t * (nj + 1), nj, lane);
+    if (lane == 0) xi2[cand] = (float)v;
+}
+
+// Detector average xi^2_C at coherent candidates: one workgroup per candidate (detector
+// I, template t, window w), wave J evaluates detector J's series at its arrival time
+// s_J = c + tau[p][J] - tau[p][I] in the candidate's direction p; the first thread
+// averages the n_det values in detector order.
+constexpr int kMaxNetDet = 8;
+
+__global__ __launch_bounds__(kWave *kMaxNetDet) void xi2_network_kernel(
+    const float2 *__restrict__ z, int32_t n_det, int32_t n_templates, int32_t n,
+    const int32_t *__restrict__ index, const int32_t *__restrict__ pix, int32_t n_win,
+    const int32_t *__restrict__ tau, int32_t n_pix, const double2 *__restrict__ R, int32_t nj,
+    float *__restrict__ xi2_det, float *__restrict__ xi2_c) {
+    __shared__ double part[kMaxNetDet];
+    const int64_t cand = blockIdx.x;                 // ((I * T) + t) * n_win + w
+    const int64_t row = cand / n_win;                // I * T + t
+    const int t = (int)(row % n_templates);
+    const int I = (int)(row / n_templates);
+    const int J = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int c = index[cand];
+    const int p = pix[cand];
+    bool ok = c >= 0 && p >= 0 && p < n_pix;
+    if (ok) {
+        const int32_t *tp = tau + (int64_t)p * n_det;
+        for (int q = 0; q < n_det; ++q) {
+            const int s = c + tp[q] - tp[I];
+            ok = ok && s - nj >= 0 && s + nj < n;
+        }
+    }
+    if (!ok) {
+        if (lane == 0 && xi2_det != nullptr) xi2_det[cand * n_det + J] = __builtin_nanf("");
+        if (threadIdx.x == 0) xi2_c[cand] = __builtin_nanf("");
+        return;
+    }
+    const int s = c + tau[(int64_t)p * n_det + J] - tau[(int64_t)p * n_det + I];
+    const float2 *zr = z + ((int64_t)J * n_templates + t) * n;
+    const double v = xi2_wave(zr, s, R + (int64_t)t * (nj + 1), nj, lane);
+    if (lane == 0) {
+        part[J] = v;
+        if (xi2_det != nullptr) xi2_det[cand * n_det + J] = (float)v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int q = 0; q < n_det; ++q) sum += part[q];
+        xi2_c[cand] = (float)(sum / n_det);
+    }
 }
 
 }  // namespace
@@ -166,6 +221,22 @@ hipError_t launch_xi2(const float2 *z, int32_t n_det, int32_t n_templates, int32
     if (cands <= 0) return hipSuccess;
     hipLaunchKernelGGL(xi2_kernel, dim3((unsigned)cands), dim3(kWave), 0, s, z, n_templates, n, index,
                        n_win, R, nj, xi2);
+    return hipGetLastError();
+}
+
+}  // namespace spiir
+
+namespace spiir {
+
+hipError_t launch_xi2_network(const float2 *z, int32_t n_det, int32_t n_templates, int32_t n,
+                              const int32_t *index, const int32_t *pix, int32_t n_win,
+                              const int32_t *tau, int32_t n_pix, const double2 *R, int32_t nj,
+                              float *xi2_det, float *xi2_c, hipStream_t s) {
+    const int64_t cands = (int64_t)n_det * n_templates * n_win;
+    if (cands <= 0) return hipSuccess;
+    hipLaunchKernelGGL(xi2_network_kernel, dim3((unsigned)cands), dim3(kWave * n_det), 0, s, z,
+                       n_det, n_templates, n, index, pix, n_win, tau, n_pix, R, nj, xi2_det,
+                       xi2_c);
     return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ EXPORTS = (
     "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count", "spiir_forward",
     "spiir_backward", "spiir_bank_set_coeffs", "spiir_bank_noise_power", "spiir_triggers",
     "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent", "spiir_triggers_noalloc",
+    "spiir_xi2_network",
 )
 
 
@@ -108,6 +109,9 @@ def load():
     lib.spiir_bank_autocorr.argtypes = [_P, ctypes.c_int32, _P, _P]
     lib.spiir_xi2.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                               _P, ctypes.c_int32, _P, _P]
+    lib.spiir_xi2_network.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                      ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int32, _P,
+                                      _P, _P]
     lib.spiir_coherent.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                    ctypes.c_int32, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P,
                                    _P, _P, _P]
@@ -118,7 +122,7 @@ def load():
                  "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count",
                  "spiir_forward", "spiir_backward", "spiir_bank_set_coeffs",
                  "spiir_bank_noise_power", "spiir_triggers", "spiir_triggers_noalloc",
-                 "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent"):
+                 "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent", "spiir_xi2_network"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -439,6 +443,31 @@ def xi2(z, index, R, nj: int, stream=None):
     _check("spiir_xi2", load().spiir_xi2(z.data_ptr(), D, T, n, index.data_ptr(), W, R.data_ptr(),
                                          int(nj), out.data_ptr(), _stream_ptr(stream)))
     return out
+
+
+def xi2_network(z, index, pix, tau, R, nj: int, stream=None):
+    """xi^2 of every detector at coherent candidates and their mean xi^2_C (Sec. II.C.1).
+
+    ``z`` cuda complex64 [D][T][n]; ``index``, ``pix`` cuda int32 [D][T][W] (candidate
+    samples and their sky directions, -1 = none); ``tau`` cuda int32 [P][D]; ``R`` cuda
+    complex128 [T][nj+1].  Returns (xi2_det [D][T][W][D], xi2_c [D][T][W]) float32.
+    """
+    import torch
+    assert z.is_cuda and z.dtype == torch.complex64 and z.is_contiguous() and z.dim() == 3
+    D, T, n = (int(v) for v in z.shape)
+    W = int(index.shape[2])
+    for a, dt in ((index, torch.int32), (pix, torch.int32), (tau, torch.int32)):
+        assert a.is_cuda and a.dtype == dt and a.is_contiguous()
+    assert tuple(index.shape) == (D, T, W) and tuple(pix.shape) == (D, T, W)
+    assert tau.dim() == 2 and tau.shape[1] == D
+    assert R.dtype == torch.complex128 and R.is_contiguous() and tuple(R.shape) == (T, nj + 1)
+    per = torch.empty((D, T, W, D), dtype=torch.float32, device=z.device)
+    mean = torch.empty((D, T, W), dtype=torch.float32, device=z.device)
+    _check("spiir_xi2_network", load().spiir_xi2_network(
+        z.data_ptr(), D, T, n, index.data_ptr(), pix.data_ptr(), W, tau.data_ptr(),
+        int(tau.shape[0]), R.data_ptr(), int(nj), per.data_ptr(), mean.data_ptr(),
+        _stream_ptr(stream)))
+    return per, mean
 
 
 def coherent(z, index, U, tau, shifts, stream=None):

@@ -108,6 +108,12 @@ def test_null_and_shape_errors_without_gpu():
     assert lib.spiir_coherent(None, 1, 2, 100, *args) == spiir.SPIIR_E_INVAL    # one detector
     assert lib.spiir_coherent(None, 9, 2, 100, *args) == spiir.SPIIR_E_INVAL    # too many
     assert lib.spiir_coherent(None, 3, 2, 100, *args) == spiir.SPIIR_E_INVAL    # NULL buffers
+    f = lib.spiir_xi2_network
+    assert f(None, 0, 2, 100, None, None, 1, None, 4, None, 5, None, None, None) == spiir.SPIIR_E_INVAL  # n_det 0
+    assert f(None, 9, 2, 100, None, None, 1, None, 4, None, 5, None, None, None) == spiir.SPIIR_E_INVAL  # 9 detectors
+    assert f(None, 3, 2, 100, None, None, 1, None, 4, None, 0, None, None, None) == spiir.SPIIR_E_INVAL  # nj 0
+    assert f(None, 3, 2, 100, None, None, 1, None, 4, None, 5, None, None, None) == spiir.SPIIR_E_INVAL  # NULLs
+    assert f(None, 3, 0, 100, None, None, 1, None, 4, None, 5, None, None, None) == spiir.SPIIR_OK      # empty
     assert lib.spiir_peaks(None, 0, 16, 8, None, None, None) == spiir.SPIIR_OK        # empty no-op
     assert lib.spiir_peaks(None, -1, 16, 8, None, None, None) == spiir.SPIIR_E_INVAL
 
