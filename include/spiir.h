@@ -342,7 +342,10 @@ spiir_status spiir_backward(spiir_bank *bank, const float *x, int32_t n, const f
 /*
  * Replace the coefficients with device arrays a, b (complex64 [F], original filter
  * order); delays and layout are kept.  Enqueued on `stream`; the values are not
- * validated (the caller keeps |a_k| < 1).  FP32 scan mode only.
+ * validated (the caller keeps |a_k| < 1).  In the block mode the matrix-core operands
+ * (Section II.B.1's filters unrolled over a time block) are regenerated from the new
+ * coefficients on the GPU, also enqueued on `stream`; the stream state is kept either
+ * way (call spiir_bank_reset to start a new stream).
  */
 spiir_status spiir_bank_set_coeffs(spiir_bank *bank, const float *a, const float *b, void *stream);
 

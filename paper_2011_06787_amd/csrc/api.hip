@@ -896,13 +896,15 @@ spiir_status spiir_backward(spiir_bank *h, const float *x, int32_t n, const floa
 spiir_status spiir_bank_set_coeffs(spiir_bank *h, const float *a, const float *b, void *stream) {
     if (h == nullptr) return fail(SPIIR_E_INVAL, "bank is NULL");
     spiir::Bank &bk = h->bk;
-    if (bk.mode != SPIIR_MODE_FP32_SCAN)
-        return fail(SPIIR_E_UNSUPPORTED, "spiir_bank_set_coeffs needs the FP32 scan mode");
     if (bk.n_filters > 0 && (a == nullptr || b == nullptr)) return fail(SPIIR_E_INVAL, "a or b is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     bk.last_stream = s;
-    SPIIR_HIP(spiir::launch_set_coeffs(bk, reinterpret_cast<const float2 *>(a),
-                                       reinterpret_cast<const float2 *>(b), s));
+    if (bk.mode == SPIIR_MODE_BF16_BLOCK)
+        SPIIR_HIP(spiir::launch_block_set_coeffs(bk, reinterpret_cast<const float2 *>(a),
+                                                 reinterpret_cast<const float2 *>(b), s));
+    else
+        SPIIR_HIP(spiir::launch_set_coeffs(bk, reinterpret_cast<const float2 *>(a),
+                                           reinterpret_cast<const float2 *>(b), s));
     return SPIIR_OK;
 }
 

@@ -141,6 +141,13 @@ struct Bank {
     int64_t xs_stride = 0;       // per-detector length of the split input
     uint16_t *d_xs = nullptr;    // [2][D][xs_stride]: input from -hist_pad, bf16 hi / lo planes
     float2 *d_zbuf = nullptr;    // [D][T][max_chunk] when the caller passes no z
+    float2 *d_ga = nullptr;      // [n_fpad] coefficients in sorted-padded order (0 for padding)
+    float2 *d_gb = nullptr;
+    int32_t *d_gd = nullptr;     // [n_fpad] delays in sorted-padded order (padding: past every band)
+    int32_t *d_wblk = nullptr;   // [n_wblocks] tile of every input-to-state operand block
+    int64_t n_wblocks = 0;
+    int32_t max_p_blocks = 0;    // output-operand blocks of the largest template: state part
+    int32_t max_m_blocks = 0;    // and input part
 
     int64_t device_bytes = 0;
     hipStream_t last_stream = nullptr;
@@ -194,6 +201,8 @@ hipError_t launch_xi2_network(const float2 *z, int32_t n_det, int32_t n_template
                               const int32_t *index, const int32_t *pix, int32_t n_win,
                               const int32_t *tau, int32_t n_pix, const double2 *R, int32_t nj,
                               float *xi2_det, float *xi2_c, hipStream_t s);
+hipError_t launch_block_operands(const Bank &bk, hipStream_t s);
+hipError_t launch_block_set_coeffs(const Bank &bk, const float2 *a, const float2 *b, hipStream_t s);
 int32_t block_state_xwin(const Bank &bk);
 size_t block_state_lds_bytes(const Bank &bk);
 hipError_t prepare_block_bf16(const Bank &bk);

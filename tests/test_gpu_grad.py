@@ -97,7 +97,7 @@ def test_set_coeffs_reloads_the_bank(gpu):
     assert oracle.rel_err(z.cpu().numpy(), oracle.filter(moved, x)).max() <= 1e-4
 
 
-def test_differentiation_rejected_in_block_mode(gpu):
+def test_differentiation_rejected_in_block_mode(gpu):  # forward / backward need the FP32 scan
     import torch
     rng = np.random.default_rng(79)
     bank = synth.draw_filters(rng, np.array([16]))
