@@ -567,7 +567,7 @@ def coherent_run(args, dev):
                        "3072 directions foreground, 768 x 100 shifts background"}
     with spiir.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=n) as sb:
         z, _, _ = sb.filter_chunk(x)
-        weight = torch.from_numpy((2.0 / sb.noise_power()).astype(np.float32)).to(dev)
+        weight = sb.trigger_weights()
         _, idx = spiir.triggers(z, weight, 4.0, fs)
         idx = torch.where((idx >= n - fs) & (idx < n - 128), idx, torch.full_like(idx, -1)).contiguous()
         args_fg = (cuda(fg.U), cuda(fg.tau), cuda(sh_fg))

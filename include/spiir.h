@@ -188,6 +188,15 @@ spiir_status spiir_peaks(const float *z, int64_t rows, int32_t n, int32_t window
 spiir_status spiir_bank_noise_power(const spiir_bank *bank, double *power);
 
 /*
+ * The weights spiir_triggers takes, weight_t = 2 / E|z_t|^2 (0 for a template whose
+ * E|z_t|^2 is 0), computed on the GPU in FP64 with the same pair sum as
+ * spiir_bank_noise_power but from the bank's current device coefficients (so they
+ * follow spiir_bank_set_coeffs).  Enqueued on `stream`; allocates nothing.
+ *   weight  device float32 [T]
+ */
+spiir_status spiir_bank_trigger_weights(const spiir_bank *bank, float *weight, void *stream);
+
+/*
  * Single-detector candidates of Section II.C.1: at every sample the template with
  * the largest normalised SNR^2  rho2_t = |z_t|^2 * weight_t  (|z|^2 = re*re + im*im,
  * every product and sum rounded to float32; weight_t = 2 / E|z_t|^2 normalises each

@@ -705,6 +705,12 @@ spiir_status spiir_bank_noise_power(const spiir_bank *h, double *power) {
     return SPIIR_OK;
 }
 
+spiir_status spiir_bank_trigger_weights(const spiir_bank *h, float *weight, void *stream) {
+    if (h == nullptr || weight == nullptr) return fail(SPIIR_E_INVAL, "bank or weight is NULL");
+    SPIIR_HIP(spiir::launch_trigger_weights(h->bk, weight, static_cast<hipStream_t>(stream)));
+    return SPIIR_OK;
+}
+
 spiir_status spiir_triggers(const float *z, int32_t n_det, int32_t n_templates, int32_t n,
                             const float *weight, float threshold, int32_t window, void *work,
                             float *snr, int32_t *index, void *stream) {

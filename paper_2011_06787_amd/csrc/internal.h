@@ -201,6 +201,7 @@ hipError_t launch_xi2_network(const float2 *z, int32_t n_det, int32_t n_template
                               const int32_t *index, const int32_t *pix, int32_t n_win,
                               const int32_t *tau, int32_t n_pix, const double2 *R, int32_t nj,
                               float *xi2_det, float *xi2_c, hipStream_t s);
+hipError_t launch_trigger_weights(const Bank &bk, float *weight, hipStream_t s);
 hipError_t launch_block_operands(const Bank &bk, hipStream_t s);
 hipError_t launch_block_set_coeffs(const Bank &bk, const float2 *a, const float2 *b, hipStream_t s);
 int32_t block_state_xwin(const Bank &bk);

@@ -234,6 +234,71 @@ __global__ __launch_bounds__(kTrigThreads) void trigger_keys_kernel(
     }
 }
 
+// Trigger weight 2 / E|z_t|^2 of every template for unit white input, from the bank's
+// device coefficients in FP64 (Section II.C.1 normalises each quadrature of the SNR to
+// unit variance):  E|z_t|^2 = sum over ordered pairs (k, l) of the template's filters of
+// Re[ b_p conj(b_q) conj(a_q)^(d_p - d_q) / (1 - a_p conj(a_q)) ]  with (p, q) the pair
+// ordered so that d_p >= d_q.  One workgroup per template: thread k walks every l;
+// padding entries (b = 0) add nothing.  The filters of template t are the entries
+// [lo, hi) of the coefficient arrays: the slot lanes of its slices (FP32 scan layout,
+// `slices` non-NULL) or [g0, g0 + fpad) of the delay-sorted layout (block form).
+struct Cd {
+    double r, i;
+};
+__device__ __forceinline__ Cd cmul(Cd a, Cd b) { return Cd{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+
+constexpr int kWeightThreads = 256;
+
+__global__ __launch_bounds__(kWeightThreads) void trigger_weight_kernel(
+    const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
+    const Slice *__restrict__ slices, const int32_t *__restrict__ tmpl_slices,
+    const BTemplate *__restrict__ btmpl, float *__restrict__ weight) {
+    __shared__ double part[kWeightThreads / kWave];
+    const int t = blockIdx.x;
+    int64_t lo = 0, hi = 0;
+    if (slices != nullptr) {
+        const int s0 = tmpl_slices[t], s1 = tmpl_slices[t + 1];
+        if (s1 > s0) {
+            lo = (int64_t)slices[s0].slot_base * kWave;
+            hi = (int64_t)(slices[s1 - 1].slot_base + slices[s1 - 1].n_slots) * kWave;
+        }
+    } else {
+        lo = btmpl[t].g0;
+        hi = lo + btmpl[t].fpad;
+    }
+    double acc = 0.0;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += kWeightThreads) {
+        const float2 bk = cb[k];
+        if (bk.x == 0.0f && bk.y == 0.0f) continue;
+        for (int64_t l = lo; l < hi; ++l) {
+            const float2 bl = cb[l];
+            if (bl.x == 0.0f && bl.y == 0.0f) continue;
+            const bool kp = cd[k] >= cd[l];
+            const int64_t p = kp ? k : l, q = kp ? l : k;
+            const Cd ap{(double)ca[p].x, (double)ca[p].y};
+            const Cd aq{(double)ca[q].x, -(double)ca[q].y};                 // conj(a_q)
+            const Cd num = cmul(Cd{(double)cb[p].x, (double)cb[p].y},
+                                Cd{(double)cb[q].x, -(double)cb[q].y});     // b_p conj(b_q)
+            Cd pw{1.0, 0.0}, base = aq;
+            for (int e = cd[p] - cd[q]; e > 0; e >>= 1) {
+                if (e & 1) pw = cmul(pw, base);
+                base = cmul(base, base);
+            }
+            const Cd nu = cmul(num, pw);
+            const Cd den{1.0 - (ap.r * aq.r - ap.i * aq.i), -(ap.r * aq.i + ap.i * aq.r)};
+            acc += (nu.r * den.r + nu.i * den.i) / (den.r * den.r + den.i * den.i);
+        }
+    }
+    for (int off = kWave / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kWeightThreads / kWave; ++w) tot += part[w];
+        weight[t] = tot > 0.0 ? (float)(2.0 / tot) : 0.0f;
+    }
+}
+
 __global__ void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t count) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
          k += (int64_t)gridDim.x * blockDim.x)
@@ -365,6 +430,18 @@ hipError_t launch_triggers_noalloc(const float2 *z, int32_t n_det, int32_t n_tem
     // the same kernels as launch_triggers; the slots are cleared there by a kernel
     return launch_triggers(z, n_det, n_templates, n, weight, threshold, window, work, snr, index,
                            s);
+}
+
+hipError_t launch_trigger_weights(const Bank &bk, float *weight, hipStream_t s) {
+    if (bk.n_templates <= 0) return hipSuccess;
+    if (bk.mode == SPIIR_MODE_BF16_BLOCK)
+        hipLaunchKernelGGL(trigger_weight_kernel, dim3(bk.n_templates), dim3(kWeightThreads), 0, s,
+                           bk.d_ga, bk.d_gb, bk.d_gd, nullptr, nullptr, bk.d_btmpl, weight);
+    else
+        hipLaunchKernelGGL(trigger_weight_kernel, dim3(bk.n_templates), dim3(kWeightThreads), 0, s,
+                           bk.d_a, bk.d_b, bk.d_delay, bk.d_slices, bk.d_tmpl_slices, nullptr,
+                           weight);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t s) {

@@ -32,7 +32,7 @@ EXPORTS = (
     "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count", "spiir_forward",
     "spiir_backward", "spiir_bank_set_coeffs", "spiir_bank_noise_power", "spiir_triggers",
     "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent", "spiir_triggers_noalloc",
-    "spiir_xi2_network",
+    "spiir_xi2_network", "spiir_bank_trigger_weights",
 )
 
 
@@ -107,6 +107,7 @@ def load():
     lib.spiir_triggers_noalloc.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                            ctypes.c_float, ctypes.c_int32, _P, _P, _P]
     lib.spiir_bank_autocorr.argtypes = [_P, ctypes.c_int32, _P, _P]
+    lib.spiir_bank_trigger_weights.argtypes = [_P, _P, _P]
     lib.spiir_xi2.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                               _P, ctypes.c_int32, _P, _P]
     lib.spiir_xi2_network.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
@@ -122,7 +123,8 @@ def load():
                  "spiir_bank_set_timing", "spiir_bank_kernel_time", "spiir_ckpt_count",
                  "spiir_forward", "spiir_backward", "spiir_bank_set_coeffs",
                  "spiir_bank_noise_power", "spiir_triggers", "spiir_triggers_noalloc",
-                 "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent", "spiir_xi2_network"):
+                 "spiir_bank_autocorr", "spiir_xi2", "spiir_coherent", "spiir_xi2_network",
+                 "spiir_bank_trigger_weights"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -284,6 +286,15 @@ class SpiirBank:
         out = np.empty(self.n_templates, dtype=np.float64)
         _check("spiir_bank_noise_power", load().spiir_bank_noise_power(self._h, out.ctypes.data))
         return out
+
+    def trigger_weights(self, stream=None):
+        """2 / E|z_t|^2 per template (cuda float32 [T]), computed on the GPU from the
+        bank's current coefficients (Sec. II.C.1 normalisation)."""
+        import torch
+        w = torch.empty(self.n_templates, dtype=torch.float32, device="cuda")
+        _check("spiir_bank_trigger_weights",
+               load().spiir_bank_trigger_weights(self._h, w.data_ptr(), _stream_ptr(stream)))
+        return w
 
     def autocorr(self, nj: int = 175, stream=None):
         """R_t[j], j = 0..nj, of each template's impulse response (Sec. II.C.1): cuda

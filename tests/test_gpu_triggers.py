@@ -90,3 +90,24 @@ def test_triggers_threshold_is_strict(gpu):
     snr, idx = gpu.triggers(torch.from_numpy(z).cuda(), torch.from_numpy(w).cuda(), 4.0, window)
     assert np.array_equal(idx.cpu().numpy(), exp_idx)
     assert np.array_equal(snr.cpu().numpy(), exp_snr)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_trigger_weights_on_the_gpu(gpu, mode):
+    """2 / E|z_t|^2 from the bank's device coefficients equals 2 / the oracle's closed-form
+    noise power (float32 rounding of an FP64 value), also for a template without filters,
+    and follows set_coeffs."""
+    import torch
+    rng = np.random.default_rng(95 + mode)
+    counts = np.array([30, 0, 200, 64, 1])
+    bank = synth.draw_filters(rng, counts)
+    other = synth.draw_filters(np.random.default_rng(97 + mode), counts)
+    with gpu.SpiirBank.from_bank(bank, max_chunk=256, mode=mode) as sb:
+        w = sb.trigger_weights().cpu().numpy()
+        sb.set_coeffs(torch.from_numpy(other.a).cuda(), torch.from_numpy(other.b).cuda())
+        w2 = sb.trigger_weights().cpu().numpy()
+    for got, bk in ((w, bank), (w2, synth.Bank(bank.offsets, other.a, other.b, bank.d))):
+        p = oracle.noise_power(bk)
+        assert got[1] == 0.0 and p[1] == 0.0
+        ok = p > 0
+        assert np.allclose(got[ok], (2.0 / p[ok]).astype(np.float32), rtol=2e-7, atol=0)

@@ -120,7 +120,7 @@ def test_xi2_network_after_gpu_triggers_and_coherent_search(gpu):
     cuda = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=x.shape[1]) as sb:
         z, _, _ = sb.filter_chunk(torch.from_numpy(x).cuda())
-        weight = torch.from_numpy((2.0 / sb.noise_power()).astype(np.float32)).cuda()
+        weight = sb.trigger_weights()
         R = sb.autocorr(nj)
     _, idx = spiir.triggers(z, weight, 2.5, 512)
     shifts = torch.zeros((1, D), dtype=torch.int32, device="cuda")
