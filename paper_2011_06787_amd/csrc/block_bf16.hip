@@ -67,10 +67,11 @@ __global__ void split_input_kernel(const float *__restrict__ x, int32_t n,
 
 // Block-to-block carry of one chunk of kChunk blocks for the lane's filter f and its
 // group q of kChunk/4 consecutive blocks:  Y[b+1] = A Y[b] + S[b]  (A = a^L).
-// A two-level scan: every lane runs its group from a zero state, the four group
-// totals are combined through LDS (Ystart[q+1] = A^len Ystart[q] + T[q]), and each
-// lane then adds A^c Ystart[q] to its local states.  The state entering every block
-// is written as bf16 hi + lo.  R is double for long-pole filters, float otherwise.
+// A two-level scan in two passes: every lane runs its group from a zero state for the
+// group's total, the four group totals are combined through LDS (Ystart[q+1] = A^len
+// Ystart[q] + T[q]), and each lane then runs its group again from Ystart[q], writing the
+// state entering every block as bf16 hi + lo (running the group twice keeps no
+// per-block state in registers).  R is double for long-pole filters, float otherwise.
 // AG = A^kGroup (precomputed per filter).
 constexpr int kChunk = 64;
 constexpr int kGroup = kChunk / 4;
@@ -108,18 +109,13 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
                                             int f, int q, int valid_cols, C2<R> A, C2<R> AG,
                                             C2<R> &y_prev, uint32_t *yh, uint32_t *yl,
                                             int64_t row_len2, int64_t col0) {
-    // local scan of the group from zero
+    // pass 1: the group's total from a zero state
     const int c_lo = q * kGroup;
     const int len = max(0, min(kGroup, valid_cols - c_lo));
-    C2<R> loc[kGroup];
     C2<R> y{0, 0};
-#pragma unroll
-    for (int c = 0; c < kGroup; ++c) {
-        loc[c] = y;   // local state entering block c_lo + c
-        if (c < len) {
-            const C2<R> sv{(R)sl[2 * f][c_lo + c], (R)sl[2 * f + 1][c_lo + c]};
-            y = cfma(A, y, sv);
-        }
+    for (int c = 0; c < len; ++c) {
+        const C2<R> sv{(R)sl[2 * f][c_lo + c], (R)sl[2 * f + 1][c_lo + c]};
+        y = cfma(A, y, sv);
     }
     tot[q][f] = y;
     // sl and tot belong to this wave alone and the four lanes of a filter take the same
@@ -140,16 +136,13 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     y_prev = ynext;
-    // states entering the group's blocks
-    C2<R> pw = ystart;
-#pragma unroll
-    for (int c = 0; c < kGroup; ++c) {
-        if (c < len) {
-            const float yr = (float)(pw.r + loc[c].r), yi = (float)(pw.i + loc[c].i);
-            const int64_t o = (col0 + c_lo + c) * row_len2;
-            store_split(yh + o, yl + o, yr, yi);
-            pw = cmul(A, pw);
-        }
+    // pass 2: the states entering the group's blocks, from the group's true start
+    y = ystart;
+    for (int c = 0; c < len; ++c) {
+        const int64_t o = (col0 + c_lo + c) * row_len2;
+        store_split(yh + o, yl + o, (float)y.r, (float)y.i);
+        const C2<R> sv{(R)sl[2 * f][c_lo + c], (R)sl[2 * f + 1][c_lo + c]};
+        y = cfma(A, y, sv);
     }
 }
 
@@ -168,7 +161,7 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
 // two uses and several workgroups share a CU.
 constexpr int kStateWaves = 4;
 constexpr int kSlFloats = 32 * (kChunk + 1);   // one wave's S rows
-constexpr int kACache = 8;                    // W' K steps kept in registers
+constexpr int kACache = 4;                    // W' K steps kept in registers
 
 __device__ __forceinline__ int skew(int p, int L) { return p + 8 * (p / L); }
 
