@@ -831,6 +831,11 @@ def main():
     if not args.no_coherent:
         result["coherent"] = coherent_run(args, dev)
     print(json.dumps(result), flush=True)
+    if result.get("scan_wait_timeouts", 0) != 0:
+        # a state hand-off wait gave up: the stream's SNR series from then on are invalid
+        print(f"bench.py: {result['scan_wait_timeouts']} state hand-off waits hit their bound",
+              file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":
