@@ -181,7 +181,8 @@ spiir_status spiir_peaks(const float *z, int64_t rows, int32_t n, int32_t window
 /*
  * ---- Trigger selection (Section II.C.1) ----
  * E|z_t|^2 for stationary white input of unit variance (the whitened strain of
- * Section II.A), per template, in FP64 on the host from the bank's coefficients:
+ * Section II.A), per template, in FP64 on the host from the coefficients given at bank
+ * creation (spiir_bank_trigger_weights uses the current device coefficients):
  *   E|z_t|^2 = sum_{k,l in t} Re[ b_k conj(b_l) conj(a_l)^(d_k-d_l) / (1 - a_k conj(a_l)) ]
  * (pairs ordered so that d_k >= d_l).  power: host double [T].  Synchronous.
  */
