@@ -137,7 +137,8 @@ typedef struct {
     int32_t time_tile;        /* 0 when the scan is not time-split */
     int32_t scan_waves;       /* grid of the persistent scan */
     int32_t block_len;
-    int32_t n_long_pole;      /* block form: filters carried in FP64 */
+    int32_t n_long_pole;      /* block form: filters carried in FP64 (counted from the
+                                 coefficients given at creation) */
     int32_t scan_wait_timeouts; /* state hand-off waits (persistent or balanced scan) that hit their
                                    bound since creation or the last reset: the stream's results
                                    from that packet on are invalid; 0 normally */

@@ -92,13 +92,13 @@ __global__ __launch_bounds__(256) void block_w_kernel(const WTile *__restrict__ 
 
 // Output operand, state part: block (template t, K step ks < nks_p, row tile rt):
 // row 2j + c, K entry 2 fi + cc holds [[Re p, -Im p], [Im p, Re p]][c][cc] with
-// p = a_fi^(j+1).  grid (blocks of the largest template, T); thread (row, kk).
+// p = a_fi^(j+1).  grid (T, blocks of the largest template); thread (row, kk).
 __global__ __launch_bounds__(512) void block_p_kernel(const BTemplate *__restrict__ tmpls,
                                                       const float2 *__restrict__ ga, int32_t L,
                                                       uint16_t *__restrict__ pa) {
     const int rt_per = 2 * L / 32;
-    const BTemplate bt = tmpls[blockIdx.y];
-    const int b = blockIdx.x;
+    const BTemplate bt = tmpls[blockIdx.x];
+    const int b = blockIdx.y;
     if (b >= bt.nks_p * rt_per) return;
     const int ks = b / rt_per, rt = b % rt_per;
     const int row = threadIdx.x / 16, kk = threadIdx.x % 16;
@@ -114,15 +114,15 @@ __global__ __launch_bounds__(512) void block_p_kernel(const BTemplate *__restric
 // a contiguous run of the delay-sorted filters (found by binary search), summed in
 // sorted order in FP64.  Block (template t, K step nks_p + km, row tile rt) holds rows
 // 2j (re) and 2j+1 (im) for 16 values of j and K entries sigma - sigma_lo.
-// grid (blocks of the largest template, T); thread (j, kk).
+// grid (T, blocks of the largest template); thread (j, kk).
 __global__ __launch_bounds__(256) void block_m_kernel(const BTemplate *__restrict__ tmpls,
                                                       const float2 *__restrict__ ga,
                                                       const float2 *__restrict__ gb,
                                                       const int32_t *__restrict__ gd, int32_t L,
                                                       uint16_t *__restrict__ pa) {
     const int rt_per = 2 * L / 32;
-    const BTemplate bt = tmpls[blockIdx.y];
-    const int b = blockIdx.x;
+    const BTemplate bt = tmpls[blockIdx.x];
+    const int b = blockIdx.y;
     if (b >= bt.nks_m * rt_per) return;
     const int km = b / rt_per, rt = b % rt_per;
     const int jl = threadIdx.x / 16, kk = threadIdx.x % 16;
@@ -260,6 +260,10 @@ spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const 
     }
     bk.max_p_blocks = pmax;
     bk.max_m_blocks = mmax;
+    if (pmax > 65535 || mmax > 65535) {   // the operand kernels put them on grid.y
+        err = "block form: a template's output operand has more than 65535 blocks";
+        return SPIIR_E_UNSUPPORTED;
+    }
 
     auto alloc = [&](void **ptr, int64_t bytes) -> bool {
         bytes = (std::max<int64_t>(bytes, 16) + 255) & ~int64_t(255);
@@ -327,10 +331,10 @@ hipError_t launch_block_operands(const Bank &bk, hipStream_t s) {
         hipLaunchKernelGGL(block_w_kernel, dim3((unsigned)bk.n_wblocks), dim3(256), 0, s,
                            bk.d_wtiles, bk.d_wblk, bk.d_ga, bk.d_gb, bk.d_gd, L, bk.d_wa);
     if (bk.max_p_blocks > 0)
-        hipLaunchKernelGGL(block_p_kernel, dim3((unsigned)bk.max_p_blocks, (unsigned)T), dim3(512), 0,
+        hipLaunchKernelGGL(block_p_kernel, dim3((unsigned)T, (unsigned)bk.max_p_blocks), dim3(512), 0,
                            s, bk.d_btmpl, bk.d_ga, L, bk.d_pa);
     if (bk.max_m_blocks > 0)
-        hipLaunchKernelGGL(block_m_kernel, dim3((unsigned)bk.max_m_blocks, (unsigned)T), dim3(256), 0,
+        hipLaunchKernelGGL(block_m_kernel, dim3((unsigned)T, (unsigned)bk.max_m_blocks), dim3(256), 0,
                            s, bk.d_btmpl, bk.d_ga, bk.d_gb, bk.d_gd, L, bk.d_pa);
     return hipGetLastError();
 }
