@@ -133,12 +133,18 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
         for (int32_t p = 0; p < ns; ++p) {
             spiir::Slice sl{};
             sl.tmpl = t;
+            sl.single = ns == 1 ? 1 : 0;
             sl.n_slots = (int32_t)((part[p].size() + spiir::kWave - 1) / spiir::kWave);
             slices.push_back(sl);
             members.push_back(std::move(part[p]));
         }
     }
     tmpl_slices[T] = (int32_t)slices.size();
+    // templates the slice-sum kernel always visits (none or several slices)
+    std::vector<int32_t> multi;
+    for (int32_t t = 0; t < T; ++t)
+        if (tmpl_slices[t + 1] - tmpl_slices[t] != 1) multi.push_back(t);
+    bk.n_multi = (int32_t)multi.size();
     int64_t slot = 0;
     for (auto &sl : slices) {
         sl.slot_base = (int32_t)slot;
@@ -173,6 +179,7 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
     SPIIR_TRY(dev_alloc(bk, &bk.d_perm, lanes));
     SPIIR_TRY(dev_alloc(bk, &bk.d_slices, std::max<int64_t>(bk.n_slices, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_tmpl_slices, T + 1));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_multi_tmpl, std::max<int64_t>(bk.n_multi, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_state, lanes * bk.n_det));
     SPIIR_TRY(dev_alloc(bk, &bk.d_partial,
                         std::max<int64_t>((int64_t)bk.n_det * bk.n_slices * bk.max_chunk, 1)));
@@ -200,6 +207,7 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
     SPIIR_TRY(upload(bk.d_perm, hp, s));
     SPIIR_TRY(upload(bk.d_slices, slices, s));
     SPIIR_TRY(upload(bk.d_tmpl_slices, tmpl_slices, s));
+    if (!multi.empty()) SPIIR_TRY(upload(bk.d_multi_tmpl, multi, s));
     // the host staging vectors die at return: wait for the copies
     SPIIR_HIP(hipStreamSynchronize(s));
     return SPIIR_OK;
@@ -281,6 +289,7 @@ spiir_status plan_balanced(spiir::Bank &bk, hipStream_t s) {
     SPIIR_TRY(dev_alloc(bk, &bk.d_segs, std::max<int64_t>((int64_t)segs.size(), 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_seg_off, W + 1));
     SPIIR_TRY(dev_alloc(bk, &bk.d_split_flags, std::max<int64_t>((int64_t)bk.n_det * splits, 4)));
+    SPIIR_TRY(dev_alloc(bk, &bk.d_split_cand, std::max<int64_t>((int64_t)bk.n_det * splits, 1)));
     SPIIR_TRY(dev_alloc(bk, &bk.d_bqueue, 1));
     SPIIR_TRY(dev_alloc(bk, &bk.d_simd_tab, (int64_t)spiir::kSimdKeys * spiir::kPeerTableWords));
     SPIIR_TRY(upload(bk.d_segs, segs, s));
@@ -658,13 +667,16 @@ spiir_status spiir_filter_chunk(spiir_bank *h, const float *x, int32_t n, float 
     bk.last_stream = s;
     const bool timing = bk.timed < (int64_t)bk.ev_start.size();
     if (timing) SPIIR_HIP(hipEventRecord(bk.ev_start[bk.timed], s));
-    SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, nullptr, s));
+    float2 *zz = reinterpret_cast<float2 *>(z);
+    SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, nullptr, zz, peak, argmax, s));
     if (timing) {
         SPIIR_HIP(hipEventRecord(bk.ev_stop[bk.timed], s));
         ++bk.timed;
     }
     // slice sums, peaks and the history update in one launch
-    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), peak, argmax, x, s));
+    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, zz, peak, argmax, x,
+                                         spiir::scan_fuses_singles(bk, n, false, peak != nullptr),
+                                         s));
     return SPIIR_OK;
 }
 
@@ -874,9 +886,11 @@ spiir_status spiir_forward(spiir_bank *h, const float *x, int32_t n, float *z, f
     hipStream_t s = static_cast<hipStream_t>(stream);
     bk.last_stream = s;
     SPIIR_TRY(zero_stream_state(bk, s));
-    SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, reinterpret_cast<float2 *>(ckpt), s));
-    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, reinterpret_cast<float2 *>(z), nullptr, nullptr,
-                                         nullptr, s));
+    float2 *zz = reinterpret_cast<float2 *>(z);
+    SPIIR_HIP(spiir::launch_scan_fp32(bk, x, n, reinterpret_cast<float2 *>(ckpt), zz, nullptr,
+                                      nullptr, s));
+    SPIIR_HIP(spiir::launch_reduce_peaks(bk, n, zz, nullptr, nullptr, nullptr,
+                                         spiir::scan_fuses_singles(bk, n, true, false), s));
     return SPIIR_OK;
 }
 

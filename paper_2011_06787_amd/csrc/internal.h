@@ -52,11 +52,13 @@ struct BTemplate {
 
 // One FP32-scan work unit: up to 64 * filters_per_lane filters of one template.
 // Its filters occupy `n_slots` consecutive slots of 64 lanes starting at `slot_base`.
+// A slice that holds all of its template's filters (`single`) is the template's SNR
+// series itself: the scan writes it straight into z.
 struct Slice {
     int32_t tmpl;
     int32_t slot_base;
     int32_t n_slots;
-    int32_t pad;
+    int32_t single;
 };
 
 // Balanced FP32-scan schedule: one entry of a wave's work list, the slice's samples
@@ -108,11 +110,15 @@ struct Bank {
     float2 *d_state = nullptr;   // [D][n_slots*64]
     float *d_hist = nullptr;     // [D][hist_len]
     float2 *d_partial = nullptr; // [D][n_slices][max_chunk]
+    int32_t *d_multi_tmpl = nullptr;  // templates with other than one slice, ascending
+    int32_t n_multi = 0;
     ScanQueue *d_queue = nullptr;
     uint32_t *d_flags = nullptr; // [D][n_slices]: tiles completed (epoch-relative)
     Seg *d_segs = nullptr;             // balanced schedule: work lists of all waves
     int32_t *d_seg_off = nullptr;      // [balance_waves+1]: list of wave w is [off[w], off[w+1])
     uint32_t *d_split_flags = nullptr; // [D][n_splits]: launches whose first part has published
+    float2 *d_split_cand = nullptr;    // [D][n_splits]: peak candidate (|z|^2, index bits) that
+                                       // the first part leaves for a window it does not finish
     ScanQueue *d_bqueue = nullptr;     // balanced schedule: launch epoch, finished waves, timeouts
     uint32_t *d_simd_tab = nullptr;    // balanced schedule: per-SIMD progress of co-resident waves
     float2 *d_bwd_part = nullptr;      // adjoint per-segment sums [D][bwd_max_seg][6][lanes]
@@ -166,8 +172,13 @@ struct Bank {
 size_t scan_fp32_lds_bytes(int32_t tile, int32_t hist_len);
 size_t scan_persistent_lds_bytes(int32_t tile, int32_t hist_len);
 hipError_t prepare_scan_fp32(Bank &bk);
-hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, float2 *ckpt,
-                            hipStream_t s);
+// True when the scan launch for these arguments is the balanced schedule, which then
+// also finds the peaks of every single-slice template (and writes nothing for them
+// when z is not asked for): the slice sum then skips those templates.
+bool scan_fuses_singles(const Bank &bk, int32_t n, bool with_ckpt, bool with_peaks);
+// Single-slice templates go straight into z (when given) in every schedule.
+hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, float2 *ckpt, float2 *z,
+                            float *peak, int32_t *argmax, hipStream_t s);
 size_t backward_lds_bytes(int32_t stride, int32_t hist_len, int32_t fpl);
 hipError_t prepare_backward(const Bank &bk);
 hipError_t launch_backward(const Bank &bk, const float *x, int32_t n, const float2 *gz,
@@ -175,7 +186,7 @@ hipError_t launch_backward(const Bank &bk, const float *x, int32_t n, const floa
 hipError_t launch_set_coeffs(const Bank &bk, const float2 *a, const float2 *b, hipStream_t s);
 hipError_t launch_hist_update(const Bank &bk, const float *x, int32_t n, hipStream_t s);
 hipError_t launch_reduce_peaks(const Bank &bk, int32_t n, float2 *z, float *peak,
-                               int32_t *argmax, const float *x, hipStream_t s);
+                               int32_t *argmax, const float *x, bool fused, hipStream_t s);
 hipError_t launch_peaks(const float2 *z, int64_t rows, int32_t n, int32_t window, float *peak,
                         int32_t *argmax, hipStream_t s);
 hipError_t launch_zero(void *ptr, int64_t bytes, hipStream_t s);

@@ -54,21 +54,23 @@ __device__ __forceinline__ Best block_best(Best v, Best *scratch) {
     return r;
 }
 
-// One block per row (template x detector).  The row's series is the sum of
-// `n_parts` partial series starting at `src` with stride `part_stride`.
+// One block per row (template x detector) of the rows listed in `rows` (all rows
+// when NULL; `n_list` of them).  The row's series is the sum of its template's slice
+// partials (`tmpl_parts` non-NULL) or the row itself.  A template with exactly one
+// slice was written into z by the scan: with z given it is read from there.
 // With `hist` non-NULL the grid has one more workgroup per detector (blockIdx.x ==
-// n_rows_per_det) that moves the detector's input history past the packet x (what
+// n_list) that moves the detector's input history past the packet x (what
 // hist_update_kernel does), saving a launch after the scan; `hist` and `x` are then
 // both non-NULL.
 __global__ __launch_bounds__(kPeakThreads) void reduce_peaks_kernel(
     const float2 *__restrict__ src_all, const int32_t *__restrict__ tmpl_parts, int32_t parts_per_det,
     int32_t part_stride, int32_t n, int32_t n_rows_per_det, float2 *__restrict__ z,
     float *__restrict__ peak, int32_t *__restrict__ argmax, int32_t window, int32_t n_win,
-    float *__restrict__ hist, int32_t hist_len, const float *__restrict__ x) {
+    float *__restrict__ hist, int32_t hist_len, const float *__restrict__ x,
+    const int32_t *__restrict__ rows, int32_t n_list) {
     __shared__ Best scratch[kPeakThreads / kWave];
-    const int t = blockIdx.x;
     const int det = blockIdx.y;
-    if (t == n_rows_per_det) {
+    if ((int)blockIdx.x == n_list) {
         // the history workgroup: every old value is read before any is written
         constexpr int kPer = (kMaxDelay + kPeakThreads) / kPeakThreads;
         float *h = hist + (int64_t)det * hist_len;
@@ -92,6 +94,7 @@ __global__ __launch_bounds__(kPeakThreads) void reduce_peaks_kernel(
         return;
     }
     if (z == nullptr && peak == nullptr) return;   // only the history was asked for
+    const int t = rows != nullptr ? rows[blockIdx.x] : (int)blockIdx.x;
     int p0, np;
     if (tmpl_parts != nullptr) {
         p0 = tmpl_parts[t];
@@ -100,9 +103,12 @@ __global__ __launch_bounds__(kPeakThreads) void reduce_peaks_kernel(
         p0 = t;
         np = 1;
     }
-    const float2 *src = src_all + ((int64_t)det * parts_per_det + p0) * part_stride;
     const int64_t row = (int64_t)det * n_rows_per_det + t;
-    float2 *zr = z != nullptr ? z + row * n : nullptr;
+    const bool in_z = tmpl_parts != nullptr && np == 1 && z != nullptr;
+    const float2 *src = in_z ? z + row * n
+                             : src_all + ((int64_t)det * parts_per_det + p0) * part_stride;
+    float2 *zr = z != nullptr && !in_z ? z + row * n : nullptr;
+    if (zr == nullptr && peak == nullptr) return;
     for (int w = 0; w < n_win; ++w) {
         const int lo = w * window;
         const int hi = min(lo + window, n);
@@ -329,16 +335,21 @@ __global__ void zero_kernel(float4 *__restrict__ p, int64_t n4) {
 }  // namespace
 
 hipError_t launch_reduce_peaks(const Bank &bk, int32_t n, float2 *z, float *peak, int32_t *argmax,
-                               const float *x, hipStream_t s) {
+                               const float *x, bool fused, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int32_t window = bk.peak_window > 0 ? bk.peak_window : n;
     const int32_t n_win = (n + window - 1) / window;
     const bool hist = bk.hist_len > 0 && x != nullptr;
-    if (!hist && z == nullptr && peak == nullptr) return hipSuccess;
-    hipLaunchKernelGGL(reduce_peaks_kernel, dim3(bk.n_templates + (hist ? 1 : 0), bk.n_det),
-                       dim3(kPeakThreads), 0, s, bk.d_partial, bk.d_tmpl_slices, bk.n_slices,
-                       bk.max_chunk, n, bk.n_templates, z, peak, argmax, window, n_win,
-                       hist ? bk.d_hist : nullptr, bk.hist_len, x);
+    // after a scan that finished its single-slice templates, only the others are left
+    const int32_t n_list = fused ? bk.n_multi : bk.n_templates;
+    const bool rows = z != nullptr || peak != nullptr;
+    const int32_t grid_x = (rows ? n_list : 0) + (hist ? 1 : 0);
+    if (grid_x == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_peaks_kernel, dim3(grid_x, bk.n_det), dim3(kPeakThreads), 0, s,
+                       bk.d_partial, bk.d_tmpl_slices, bk.n_slices, bk.max_chunk, n,
+                       bk.n_templates, z, peak, argmax, window, n_win,
+                       hist ? bk.d_hist : nullptr, bk.hist_len, x,
+                       fused ? bk.d_multi_tmpl : nullptr, rows ? n_list : 0);
     return hipGetLastError();
 }
 
@@ -353,7 +364,7 @@ hipError_t launch_peaks(const float2 *z, int64_t rows, int32_t n, int32_t window
         hipLaunchKernelGGL(reduce_peaks_kernel, dim3((unsigned)cnt, 1), dim3(kPeakThreads), 0, s,
                            z + r0 * n, nullptr, 0, n, n, (int32_t)cnt, nullptr,
                            peak + r0 * n_win, argmax + r0 * n_win, window, n_win, nullptr, 0,
-                           nullptr);
+                           nullptr, nullptr, (int32_t)cnt);
     }
     return hipGetLastError();
 }

@@ -25,6 +25,7 @@
 // fixed set of resident waves, each with a host-planned list of equal total work in
 // which slices may be cut in time between two waves.
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "internal.h"
@@ -133,8 +134,10 @@ __device__ __forceinline__ void load_window(float *__restrict__ win, const float
     }
 }
 
+// Returns the slice's sum of sample s0 + reduce_sample(lane), which the first lane of
+// every quad also stores at out[reduce_sample(lane)] when out is given.
 template <int MAXM, int M, bool TAIL>
-__device__ __forceinline__ void sub_tile_m(const float *__restrict__ win, int red_sample,
+__device__ __forceinline__ float2 sub_tile_m(const float *__restrict__ win, int red_sample,
                                            int lane, int s0, int valid,
                                            const float (&ar)[MAXM], const float (&ai)[MAXM],
                                            const float (&br)[MAXM], const float (&bi)[MAXM],
@@ -185,13 +188,14 @@ __device__ __forceinline__ void sub_tile_m(const float *__restrict__ win, int re
         }
     }
     const float2 v = reduce_lanes(acc, lane);
-    if ((lane & 3) == 0 && (!TAIL || red_sample < valid)) out[red_sample] = v;
+    if (out != nullptr && (lane & 3) == 0 && (!TAIL || red_sample < valid)) out[red_sample] = v;
+    return v;
 }
 
 // One sub-tile for a wave whose slice has m (1..MAXM, wave-uniform) filters per lane:
 // a scalar branch to the variant compiled for exactly m.
 template <int MAXM, bool TAIL>
-__device__ __forceinline__ void sub_tile(const float *__restrict__ win, int red_sample, int lane,
+__device__ __forceinline__ float2 sub_tile(const float *__restrict__ win, int red_sample, int lane,
                                          int m, int s0, int valid, const float (&ar)[MAXM],
                                          const float (&ai)[MAXM], const float (&br)[MAXM],
                                          const float (&bi)[MAXM], const int (&base)[MAXM],
@@ -200,8 +204,8 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, int red_
 #define SPIIR_SUB_TILE(M)                                                                    \
     case M:                                                                                  \
         if constexpr (M <= MAXM)                                                             \
-            sub_tile_m<MAXM, M, TAIL>(win, red_sample, lane, s0, valid, ar, ai, br, bi, base, yr, \
-                                      yi, out);                                              \
+            return sub_tile_m<MAXM, M, TAIL>(win, red_sample, lane, s0, valid, ar, ai, br, bi,  \
+                                             base, yr, yi, out);                             \
         break;
     switch (m) {
         SPIIR_SUB_TILE(1)
@@ -215,6 +219,7 @@ __device__ __forceinline__ void sub_tile(const float *__restrict__ win, int red_
     default: break;
     }
 #undef SPIIR_SUB_TILE
+    return make_float2(0.0f, 0.0f);
 }
 
 // Run fn(std::integral_constant<int, M>{}) for the wave-uniform filter count m in
@@ -248,7 +253,8 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     const int32_t *__restrict__ slice_order, int32_t n_slices,
     int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
     int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, int32_t tile_len,
-    float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg) {
+    float2 *__restrict__ ckpt, int32_t ckpt_stride, int32_t n_seg, float2 *__restrict__ z,
+    int32_t n_tmpl) {
     extern __shared__ float smem[];
     float *win = smem;
     // wave-uniform values live in scalar registers (readfirstlane), so that the
@@ -262,8 +268,10 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
     const bool active = rank < n_slices;
     const int sidx = active ? __builtin_amdgcn_readfirstlane(slice_order[rank]) : 0;
     Slice sl = active ? slices[sidx] : Slice{0, 0, 0, 0};
+    sl.tmpl = __builtin_amdgcn_readfirstlane(sl.tmpl);
     sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
     sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
+    sl.single = __builtin_amdgcn_readfirstlane(sl.single);
     const int m = sl.n_slots;
 
     float ar[MAXM], ai[MAXM], br[MAXM], bi[MAXM], yr[MAXM], yi[MAXM];
@@ -284,7 +292,9 @@ __global__ __launch_bounds__(kWave *kScanWaves) void scan_fp32_kernel(
 
     const float *xd = x + (int64_t)det * n;
     const float *hd = hist + (int64_t)det * hist_len;
-    float2 *pout = partial + ((int64_t)det * n_slices + sidx) * part_stride;
+    float2 *pout = sl.single && z != nullptr
+                       ? z + ((int64_t)det * n_tmpl + sl.tmpl) * n
+                       : partial + ((int64_t)det * n_slices + sidx) * part_stride;
     // optional checkpoints: the state entering every ckpt_stride-sample segment
     float2 *ck = ckpt != nullptr ? ckpt + (int64_t)det * n_seg * lanes_total : nullptr;
     if (ck != nullptr && active) {
@@ -398,7 +408,7 @@ struct SimdPeers {
     uint32_t slot;
     uint32_t done;
     uint32_t tick;
-    uint32_t seen[kPeerSlots];   // lane 0: the table as read at the previous exchange
+    uint32_t seen;   // lane k < kPeerSlots: slot k of the table as read at the previous exchange
 };
 
 __device__ __forceinline__ uint32_t simd_key() {
@@ -409,7 +419,7 @@ __device__ __forceinline__ uint32_t simd_key() {
 }
 
 __device__ __forceinline__ SimdPeers simd_join(uint32_t *table, int lane) {
-    SimdPeers p{table + (size_t)simd_key() * kPeerWords, 0u, 0u, 0u, {}};
+    SimdPeers p{table + (size_t)simd_key() * kPeerWords, 0u, 0u, 0u, 0u};
     uint32_t slot = 0;
     if (lane == 0)
         slot = __hip_atomic_fetch_add(p.tab + kPeerSlots, 1u, __ATOMIC_RELAXED,
@@ -432,18 +442,13 @@ __device__ __forceinline__ void simd_step(SimdPeers &p, uint32_t cost, int lane)
     if (p.slot >= kPeerSlots) return;
     p.done += cost;
     if (++p.tick % kPeerPeriod != 0) return;
-    uint32_t ahead = 0;
-    if (lane == 0) {
-#pragma unroll
-        for (uint32_t k = 0; k < kPeerSlots; ++k) ahead += p.seen[k] > p.done;
-    }
-    set_priority(__builtin_amdgcn_readfirstlane(ahead));
-    if (lane == 0) {
+    // one slot per lane: the waves ahead are the lanes whose slot beats this progress
+    const uint64_t ahead = __builtin_amdgcn_ballot_w64((uint32_t)lane < kPeerSlots && p.seen > p.done);
+    set_priority((uint32_t)__builtin_popcountll(ahead));
+    if (lane == 0)
         __hip_atomic_store(p.tab + p.slot, p.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-        for (uint32_t k = 0; k < kPeerSlots; ++k)
-            p.seen[k] = __hip_atomic_load(p.tab + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
+    if ((uint32_t)lane < kPeerSlots)
+        p.seen = __hip_atomic_load(p.tab + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ void simd_leave(SimdPeers &p, int lane) {
@@ -472,6 +477,96 @@ __device__ __forceinline__ int phi_sample(int32_t phi, int32_t n) {
 // slice runs first in its wave while the later part runs last in its own, so the
 // state hand-off between them rarely waits.  The window x[-hist_len, n) of the
 // workgroup's detector is loaded into LDS once for all its waves.
+// Peak search of a single-slice template inside the balanced scan (one candidate per
+// template per window, Section II.C.1), with the slice-sum kernel's decision: |z|^2
+// as two rounded products and a rounded sum, the largest value winning and the
+// lowest index among equal ones.  It runs when a wave has finished its part
+// [t0, t1) of the slice: the wave reads back the series it has just written (from
+// its own compute unit's L2) one window at a time, so the sub-tile loop carries
+// no extra registers.  Windows are whole sub-tiles or the whole packet; a window
+// that a cut splits is closed by the later part, from the candidate the earlier
+// part leaves next to its state.
+// Outputs of the fused peak search (peak NULL: not fused).
+struct FusedPeaks {
+    float *peak;       // [D][T][n_win]
+    int32_t *argmax;   // [D][T][n_win]
+    float2 *cand;      // [D][n_splits]
+    int32_t window;
+    int32_t n_win;
+};
+
+struct PeakBest {
+    float p;    // |z|^2 (-1 before the first sample)
+    int32_t i;  // index in the window
+};
+
+__device__ __forceinline__ float abs2_rn(float re, float im) {
+#pragma clang fp contract(off)
+    const float rr = re * re;
+    const float ii = im * im;
+    return rr + ii;
+}
+
+__device__ __forceinline__ PeakBest peak_better(PeakBest a, PeakBest b) {
+    return (b.p > a.p || (b.p == a.p && b.i < a.i)) ? b : a;
+}
+
+__device__ __forceinline__ void segment_peaks(const float2 *__restrict__ row, int t0, int t1, int n,
+                                           int window, const float2 *cand_in,
+                                           float2 *cand_out, float *__restrict__ pk,
+                                           int32_t *__restrict__ am, int lane) {
+    constexpr int kRb = 8;   // loads in flight per lane
+    wait_memory();           // this wave's stores of the series have completed
+    PeakBest best{-1.0f, INT_MAX};
+    if (cand_in != nullptr) {
+        const float2 c = load_coherent(cand_in);
+        best = PeakBest{c.x, __float_as_int(c.y)};
+    }
+    int cw = t0 / window;
+    for (int w0 = t0; w0 < t1;) {
+        const int wlo = cw * window;
+        const int wend = min(wlo + window, t1);
+        PeakBest b{-1.0f, INT_MAX};
+        for (int i0 = w0; i0 < wend; i0 += kRb * kWave) {
+            float2 v[kRb];
+#pragma unroll
+            for (int k = 0; k < kRb; ++k) {
+                const int i = i0 + k * kWave + lane;
+                v[k] = i < wend ? load_coherent(row + i) : make_float2(0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int k = 0; k < kRb; ++k) {
+                const int i = i0 + k * kWave + lane;
+                const float p = abs2_rn(v[k].x, v[k].y);
+                if (i < wend && p > b.p) {   // a lane's samples increase: first one kept
+                    b.p = p;
+                    b.i = i - wlo;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            PeakBest o;
+            o.p = __shfl_xor(b.p, off);
+            o.i = __shfl_xor(b.i, off);
+            b = peak_better(b, o);
+        }
+        best = peak_better(best, b);
+        if (wend == wlo + window || wend == n) {
+            if (lane == 0) {
+                pk[cw] = sqrtf(best.p);
+                am[cw] = best.i;
+            }
+            best = PeakBest{-1.0f, INT_MAX};
+            ++cw;
+        } else if (lane == 0) {
+            // the segment ends inside the window: the later part finishes it
+            store_coherent(cand_out, make_float2(best.p, __int_as_float(best.i)));
+        }
+        w0 = wend;
+    }
+}
+
 // Waves per SIMD the balanced kernel must fit in registers: its planner places a
 // whole number of workgroups (one wave per SIMD each) on every compute unit, and the
 // best counts are 3 at 8 filters per lane and up to 4 at 2 or 4.
@@ -486,7 +581,8 @@ __global__ __launch_bounds__(kWave *kScanWaves) __attribute__((amdgpu_waves_per_
     int32_t n_splits, uint32_t *__restrict__ flags, ScanQueue *__restrict__ queue,
     int64_t lanes_total, const float *__restrict__ x, int32_t n, const float *__restrict__ hist,
     int32_t hist_len, float2 *__restrict__ partial, int32_t part_stride, float2 *__restrict__ ckpt,
-    int32_t ckpt_stride, int32_t n_seg, uint32_t *__restrict__ simd_tab, WaitBound wb) {
+    int32_t ckpt_stride, int32_t n_seg, uint32_t *__restrict__ simd_tab, WaitBound wb,
+    float2 *__restrict__ z, int32_t n_tmpl, FusedPeaks fp) {
     extern __shared__ float smem[];
     float *win = smem;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -513,8 +609,10 @@ __global__ __launch_bounds__(kWave *kScanWaves) __attribute__((amdgpu_waves_per_
         sg.phi1 = __builtin_amdgcn_readfirstlane(sg.phi1);
         sg.flag = __builtin_amdgcn_readfirstlane(sg.flag);
         Slice sl = slices[sg.slice];
+        sl.tmpl = __builtin_amdgcn_readfirstlane(sl.tmpl);
         sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
         sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
+        sl.single = __builtin_amdgcn_readfirstlane(sl.single);
         const int m = sl.n_slots;
         const int t0 = sg.phi0 > 0 ? phi_sample(sg.phi0, n) : 0;
         const int t1 = phi_sample(sg.phi1, n);
@@ -551,7 +649,10 @@ __global__ __launch_bounds__(kWave *kScanWaves) __attribute__((amdgpu_waves_per_
             for (int j = 0; j < MAXM; ++j)
                 if (j < m) ck[(int64_t)(sl.slot_base + j) * kWave + lane] = make_float2(yr[j], yi[j]);
         }
-        float2 *pout = partial + ((int64_t)det * n_slices + sg.slice) * part_stride;
+        // a single-slice template is its own SNR series: into z when asked for
+        float2 *pout = sl.single && z != nullptr
+                           ? z + ((int64_t)det * n_tmpl + sl.tmpl) * n
+                           : partial + ((int64_t)det * n_slices + sg.slice) * part_stride;
         const int full_end = t1 == n ? (n & ~(kSub - 1)) : t1;
         with_m<MAXM>(m, [&](auto mc) {
             constexpr int M = decltype(mc)::value;
@@ -571,8 +672,16 @@ __global__ __launch_bounds__(kWave *kScanWaves) __attribute__((amdgpu_waves_per_
         if (t1 == n && full_end < n)
             sub_tile<MAXM, true>(win, red_sample, lane, m, full_end, n - full_end, ar, ai, br, bi,
                                  base, yr, yi, pout + full_end);
+        if (sl.single && fp.peak != nullptr && t1 > t0) {
+            const int64_t prow = ((int64_t)det * n_tmpl + sl.tmpl) * fp.n_win;
+            float2 *cs = fp.cand + (int64_t)det * n_splits + (sg.flag >= 0 ? sg.flag : 0);
+            segment_peaks(pout, t0, t1, n, fp.window,
+                          sg.phi0 > 0 && t0 % fp.window != 0 ? cs : nullptr, cs, fp.peak + prow,
+                          fp.argmax + prow, lane);
+        }
         if (sg.phi1 < kPhiOne) {
-            // first part of a cut slice: publish the state for the wave that continues it
+            // first part of a cut slice: publish the state (and a peak candidate) for the
+            // wave that continues it
 #pragma unroll
             for (int j = 0; j < MAXM; ++j)
                 if (j < m)
@@ -621,7 +730,7 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
     int32_t n_slices, int32_t n_det, int64_t lanes_total, const float *__restrict__ x, int32_t n,
     const float *__restrict__ hist, int32_t hist_len, float2 *__restrict__ partial,
     int32_t part_stride, int32_t tile, ScanQueue *__restrict__ queue,
-    uint32_t *__restrict__ flags, WaitBound wb) {
+    uint32_t *__restrict__ flags, WaitBound wb, float2 *__restrict__ z, int32_t n_tmpl) {
     extern __shared__ float smem[];
     float *win = smem;
     const int lane = threadIdx.x;
@@ -643,8 +752,10 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
         const int det = code / n_slices;
         const int sidx = code % n_slices;
         Slice sl = slices[sidx];
+        sl.tmpl = __builtin_amdgcn_readfirstlane(sl.tmpl);
         sl.slot_base = __builtin_amdgcn_readfirstlane(sl.slot_base);
         sl.n_slots = __builtin_amdgcn_readfirstlane(sl.n_slots);
+        sl.single = __builtin_amdgcn_readfirstlane(sl.single);
         const int m = sl.n_slots;
         const int n0 = (int)tau * tile;
         const int T = min(tile, n - n0);
@@ -684,7 +795,9 @@ __global__ __launch_bounds__(kWave) void scan_fp32_persistent_kernel(
             }
         }
         lds_fence();  // window stores visible to every lane of the wave
-        float2 *pout = partial + ((int64_t)det * n_slices + sidx) * part_stride + n0;
+        float2 *pout = (sl.single && z != nullptr
+                            ? z + ((int64_t)det * n_tmpl + sl.tmpl) * n
+                            : partial + ((int64_t)det * n_slices + sidx) * part_stride) + n0;
         const int full = T & ~(kSub - 1);
         with_m<MAXM>(m, [&](auto mc) {
             constexpr int M = decltype(mc)::value;
@@ -780,7 +893,8 @@ hipError_t prepare_fpl(Bank &bk) {
 }
 
 template <int MAXM>
-void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStream_t s) {
+void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, float2 *z, float *peak,
+                int32_t *argmax, hipStream_t s) {
     const int64_t lanes = bk.n_slots * kWave;
     if (bk.time_tile > 0 && ckpt == nullptr) {
         const int64_t items = (int64_t)((n + bk.time_tile - 1) / bk.time_tile) * bk.n_det *
@@ -791,8 +905,10 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            bk.d_delay, bk.d_state, bk.d_slices, bk.d_order, bk.n_slices, bk.n_det,
                            lanes, x, n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk,
                            bk.time_tile, bk.d_queue, bk.d_flags,
-                           WaitBound{bk.wait_spins, bk.d_wait_flag});
+                           WaitBound{bk.wait_spins, bk.d_wait_flag}, z, bk.n_templates);
     } else if (bk.balanced) {
+        const bool fuse = peak != nullptr && scan_fuses_singles(bk, n, ckpt != nullptr, true);
+        const int32_t window = bk.peak_window > 0 ? bk.peak_window : n;
         const dim3 grid((unsigned)((bk.balance_waves + kScanWaves - 1) / kScanWaves), bk.n_det);
         hipLaunchKernelGGL(scan_fp32_balanced_kernel<MAXM>, grid, dim3(kWave * kScanWaves),
                            (size_t)bk.balance_lds, s, bk.d_a, bk.d_b, bk.d_delay,
@@ -800,7 +916,10 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            bk.balance_waves, bk.n_splits, bk.d_split_flags, bk.d_bqueue, lanes, x,
                            n, bk.d_hist, bk.hist_len, bk.d_partial, bk.max_chunk, ckpt,
                            bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride,
-                           bk.d_simd_tab, WaitBound{bk.wait_spins, bk.d_wait_flag});
+                           bk.d_simd_tab, WaitBound{bk.wait_spins, bk.d_wait_flag}, z,
+                           bk.n_templates,
+                           FusedPeaks{fuse ? peak : nullptr, fuse ? argmax : nullptr,
+                                      bk.d_split_cand, window, (n + window - 1) / window});
     } else {
         const int32_t tile = bk.scan_tile;
         const dim3 grid((bk.n_slices + kScanWaves - 1) / kScanWaves, bk.n_det);
@@ -808,7 +927,8 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStre
                            scan_fp32_lds_bytes(tile, bk.hist_len), s, bk.d_a, bk.d_b, bk.d_delay,
                            bk.d_state, bk.d_slices, bk.d_slice_order, bk.n_slices, lanes, x, n, bk.d_hist,
                            bk.hist_len, bk.d_partial, bk.max_chunk, tile, ckpt,
-                           bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride);
+                           bk.ckpt_stride, (n + bk.ckpt_stride - 1) / bk.ckpt_stride, z,
+                           bk.n_templates);
     }
 }
 
@@ -823,12 +943,21 @@ hipError_t prepare_scan_fp32(Bank &bk) {
     }
 }
 
-hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, float2 *ckpt, hipStream_t s) {
+bool scan_fuses_singles(const Bank &bk, int32_t n, bool with_ckpt, bool with_peaks) {
+    // the same choice of schedule as launch_fpl
+    if (!bk.balanced || (bk.time_tile > 0 && !with_ckpt)) return false;
+    if (!with_peaks) return true;
+    const int32_t window = bk.peak_window > 0 ? bk.peak_window : n;
+    return window >= n || window % kSub == 0;
+}
+
+hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, float2 *ckpt, float2 *z,
+                            float *peak, int32_t *argmax, hipStream_t s) {
     if (n <= 0 || bk.n_slices == 0) return hipSuccess;
     switch (bk.fpl) {
-    case 2: launch_fpl<2>(bk, x, n, ckpt, s); break;
-    case 4: launch_fpl<4>(bk, x, n, ckpt, s); break;
-    case 8: launch_fpl<8>(bk, x, n, ckpt, s); break;
+    case 2: launch_fpl<2>(bk, x, n, ckpt, z, peak, argmax, s); break;
+    case 4: launch_fpl<4>(bk, x, n, ckpt, z, peak, argmax, s); break;
+    case 8: launch_fpl<8>(bk, x, n, ckpt, z, peak, argmax, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
