@@ -295,6 +295,15 @@ def precision_comparison(args, dev):
     return out
 
 
+def multi_group_slices(bank, fpl):
+    """Filter groups (up to 64 * fpl filters of one template) that belong to templates
+    with more than one group: the library cuts a template of f filters into
+    ceil(ceil(f / 64) / fpl) groups."""
+    counts = np.diff(bank.offsets.astype(np.int64))
+    groups = ((counts + 63) // 64 + fpl - 1) // fpl
+    return int(groups[groups > 1].sum())
+
+
 def batching_run(args, dev):
     """Batching workload: 16384 templates (lognormal filter counts, 5.58M filters),
     3 detectors, 60 s streamed in 0.25-s packets; the schedule is picked by the
@@ -726,9 +735,10 @@ def main():
     # detector) and the peaks (8 B per template, window and detector)
     info = sb.info
     alg_bytes = F * 20 + F * D * 16 + D * chunk * 4 + D * T * chunk * 8 + D * T * 8
-    # not algorithmic: partial sums of the filter groups, written by the scan and read by
-    # the template sum (8 B per group, sample and detector)
-    partial_bytes = D * info.n_slices * chunk * 8
+    # not algorithmic: partial sums of the filter groups of templates with several groups,
+    # written by the scan and read by the template sum (8 B per group, sample and
+    # detector); a one-group template's series goes straight into z
+    partial_bytes = D * multi_group_slices(bank, info.filters_per_lane) * chunk * 8
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} updates/s; "
         f"scan kernel {kern_avg_s * 1e3:.3f} ms avg over {launches} launches")
 
