@@ -118,3 +118,23 @@ def test_forward_on_the_balanced_schedule(gpu):
         z, _ = bal.forward(x)
         zr, _ = sta.forward(x)
         assert torch.equal(z, zr)
+
+
+def test_balanced_packets_without_outputs_keep_the_stream(gpu):
+    """A packet that asks for neither z nor peaks still moves the state and the history:
+    the next packet's outputs equal those of a bank that produced every output."""
+    import torch
+    D, n = 2, 1024
+    bank = mixed_bank(95)
+    x = torch.from_numpy(packets(96, D, n, 3)).cuda()
+    kw = dict(n_detectors=D, max_chunk=n, filters_per_lane=4, balance_wgs=2)
+    with gpu.SpiirBank.from_bank(bank, **kw) as quiet, gpu.SpiirBank.from_bank(bank, **kw) as full:
+        for c in range(3):
+            xc = x[:, c * n:(c + 1) * n].contiguous()
+            zf, pf, af = full.filter_chunk(xc)
+            if c == 1:
+                z, p, a = quiet.filter_chunk(xc, want_z=False, want_peaks=False)
+                assert z is None and p is None
+            else:
+                z, p, a = quiet.filter_chunk(xc)
+                assert torch.equal(z, zf) and torch.equal(p, pf) and torch.equal(a, af)
