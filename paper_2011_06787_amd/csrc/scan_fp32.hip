@@ -468,15 +468,6 @@ __device__ __forceinline__ int phi_sample(int32_t phi, int32_t n) {
     return min(n, t) & ~(kSub - 1);
 }
 
-// Balanced static schedule of the one-shot scan.  The host cuts the detector's
-// slices into equal shares of work, one per resident wave (the wrap-around rule
-// for preemptive scheduling on identical machines: fill wave after wave up to the
-// mean load; a slice that does not fit is cut in time, its later part closing the
-// current wave's list and its earlier part opening the next one).  Every SIMD then
-// carries the same load whatever the slice sizes, and the earlier part of a cut
-// slice runs first in its wave while the later part runs last in its own, so the
-// state hand-off between them rarely waits.  The window x[-hist_len, n) of the
-// workgroup's detector is loaded into LDS once for all its waves.
 // Peak search of a single-slice template inside the balanced scan (one candidate per
 // template per window, Section II.C.1), with the slice-sum kernel's decision: |z|^2
 // as two rounded products and a rounded sum, the largest value winning and the
@@ -486,6 +477,7 @@ __device__ __forceinline__ int phi_sample(int32_t phi, int32_t n) {
 // no extra registers.  Windows are whole sub-tiles or the whole packet; a window
 // that a cut splits is closed by the later part, from the candidate the earlier
 // part leaves next to its state.
+
 // Outputs of the fused peak search (peak NULL: not fused).
 struct FusedPeaks {
     float *peak;       // [D][T][n_win]
@@ -567,6 +559,15 @@ __device__ __forceinline__ void segment_peaks(const float2 *__restrict__ row, in
     }
 }
 
+// Balanced static schedule of the one-shot scan.  The host cuts the detector's
+// slices into equal shares of work, one per resident wave (the wrap-around rule
+// for preemptive scheduling on identical machines: fill wave after wave up to the
+// mean load; a slice that does not fit is cut in time, its later part closing the
+// current wave's list and its earlier part opening the next one).  Every SIMD then
+// carries the same load whatever the slice sizes, and the earlier part of a cut
+// slice runs first in its wave while the later part runs last in its own, so the
+// state hand-off between them rarely waits.  The window x[-hist_len, n) of the
+// workgroup's detector is loaded into LDS once for all its waves.
 // Waves per SIMD the balanced kernel must fit in registers: its planner places a
 // whole number of workgroups (one wave per SIMD each) on every compute unit, and the
 // best counts are 3 at 8 filters per lane and up to 4 at 2 or 4.
