@@ -94,8 +94,8 @@ spiir_status upload(T *dst, const std::vector<T> &src, hipStream_t s) {
 // ceil(F_t/64) slots of 64 lanes; these are split into ceil(slots/fpl) slices of
 // near-equal slot counts (<= fpl each).  Inside a template, filters are ordered by
 // d mod 64 and dealt to the slices in that order (each next filter to the slice
-// with the lowest fill ratio), then within a slice the sorted position i goes to
-// slot i % m, lane i / m: the 64 lanes of a slot then read the input window at
+// with the lowest fill ratio); within a slice they are dealt by d mod 32 over its
+// half-waves (see below), so the lanes of a half-wave read the input window at
 // well-spread LDS banks.
 spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, const float *b,
                        const int32_t *delay, hipStream_t s) {
@@ -159,18 +159,31 @@ spiir_status plan_scan(spiir::Bank &bk, const int32_t *offsets, const float *a, 
     const int64_t lanes = slot * spiir::kWave;
     std::vector<float2> ha(lanes, make_float2(0.f, 0.f)), hb(lanes, make_float2(0.f, 0.f));
     std::vector<int32_t> hd(lanes, 0), hp(lanes, -1);
+    constexpr int32_t kHalf = spiir::kWave / 2;   // lanes whose LDS reads are served together
     for (size_t si = 0; si < slices.size(); ++si) {
-        const auto &mem = members[si];
+        std::vector<int32_t> mem = members[si];
         const int32_t m = slices[si].n_slots;
+        // LDS input reads: lane reads window[n - d]; two lanes of one half-wave whose delays
+        // agree mod 32 hit the same bank.  Sorted by d mod 32 and dealt over the slice's 2m
+        // half-waves, each residue is spread as evenly as its count allows.
+        std::stable_sort(mem.begin(), mem.end(),
+                         [&](int32_t p, int32_t q) { return (delay[p] & 31) < (delay[q] & 31); });
         for (size_t i = 0; i < mem.size(); ++i) {
-            // sorted position i -> slot i % m, lane i / m
-            const int64_t g = (int64_t)(slices[si].slot_base + (int32_t)(i % m)) * spiir::kWave +
-                              (int64_t)(i / m);
+            const int32_t hw = (int32_t)(i % (size_t)(2 * m));     // half-wave
+            const int64_t g = (int64_t)(slices[si].slot_base + hw % m) * spiir::kWave +
+                              (hw / m) * kHalf + (int64_t)(i / (size_t)(2 * m));
             const int32_t k = mem[i];
             ha[g] = make_float2(a[2 * (int64_t)k], a[2 * (int64_t)k + 1]);
             hb[g] = make_float2(b[2 * (int64_t)k], b[2 * (int64_t)k + 1]);
             hd[g] = delay[k];
             hp[g] = k;
+        }
+        // padding lanes (b = 0) read the address of the half-wave's first lane: no new bank
+        for (int32_t hw = 0; hw < 2 * m; ++hw) {
+            const int64_t g0 = (int64_t)(slices[si].slot_base + hw % m) * spiir::kWave +
+                               (hw / m) * kHalf;
+            for (int32_t l = 1; l < kHalf; ++l)
+                if (hp[g0 + l] < 0 && hp[g0] >= 0) hd[g0 + l] = hd[g0];
         }
     }
     SPIIR_TRY(dev_alloc(bk, &bk.d_a, lanes));
