@@ -138,3 +138,28 @@ def test_balanced_packets_without_outputs_keep_the_stream(gpu):
             else:
                 z, p, a = quiet.filter_chunk(xc)
                 assert torch.equal(z, zf) and torch.equal(p, pf) and torch.equal(a, af)
+
+
+@pytest.mark.parametrize("seed, D, fpl, wgs, n, window", [
+    (1, 1, 4, 2, 2048, 0), (2, 3, 8, 3, 512, 0), (3, 2, 2, 4, 1000, 0),
+    (4, 1, 4, 1, 2048, 256), (5, 3, 4, 3, 1024, 128), (6, 2, 8, 2, 768, 0)])
+def test_balanced_equals_static_on_random_banks(gpu, seed, D, fpl, wgs, n, window):
+    """Seeded random banks (empty, one-slice and many-slice templates, delays up to 2047):
+    two packets through the balanced schedule give the one-wave-per-slice schedule's z and
+    peaks bit for bit."""
+    import torch
+    rng = np.random.default_rng(1000 + seed)
+    counts = rng.integers(0, 1200, size=int(rng.integers(20, 60)))
+    counts[rng.random(counts.size) < 0.1] = 0
+    bank = synth.draw_filters(rng, counts)
+    x = torch.from_numpy(rng.standard_normal((D, 2 * n)).astype(np.float32)).cuda()
+    kw = dict(n_detectors=D, max_chunk=n, filters_per_lane=fpl, peak_window=window)
+    with gpu.SpiirBank.from_bank(bank, balance_wgs=wgs, **kw) as bal, \
+            gpu.SpiirBank.from_bank(bank, balance_wgs=0, **kw) as sta:
+        assert bal.info.balance_waves > 0
+        for c in range(2):
+            xc = x[:, c * n:(c + 1) * n].contiguous()
+            z, p, a = bal.filter_chunk(xc)
+            zr, pr, ar = sta.filter_chunk(xc)
+            assert torch.equal(z, zr) and torch.equal(p, pr) and torch.equal(a, ar)
+        assert bal.refresh_info().scan_wait_timeouts == 0
