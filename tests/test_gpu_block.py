@@ -135,3 +135,25 @@ def test_block_set_coeffs_regenerates_the_operands(gpu, block_len):
         z2 = z2.cpu().numpy()
     assert np.array_equal(z1, z2)
     assert oracle.rel_err(z1, oracle.filter(moved, x)).max() <= TOL_BF16
+
+
+@pytest.mark.parametrize("block_len", [64, 128])
+def test_block_form_is_deterministic_across_detectors_and_chunks(gpu, block_len):
+    """Three detectors and several 64-block chunks per detector: two banks given the
+    same packet return bit-identical z (the block form has no order-dependent step), and
+    the result stays within the oracle's tolerance."""
+    import torch
+    rng = np.random.default_rng(31 + block_len)
+    bank = synth.draw_filters(rng, rng.integers(100, 700, size=24))
+    D, n = 3, 160 * block_len                       # 160 blocks: chunks of 64, 64, 32
+    x = torch.from_numpy(rng.standard_normal((D, n)).astype(np.float32)).cuda()
+    kw = dict(n_detectors=D, max_chunk=n, mode=gpu.MODE_BF16_BLOCK, block_len=block_len)
+    zs = []
+    for _ in range(2):
+        with gpu.SpiirBank.from_bank(bank, **kw) as sb:
+            z, _, _ = sb.filter_chunk(x, want_peaks=False)
+            torch.cuda.synchronize()
+            zs.append(z.clone())
+    assert torch.equal(zs[0], zs[1])
+    err = oracle.rel_err(zs[0].cpu().numpy(), oracle.filter(bank, x.cpu().numpy()))
+    assert err.max() <= TOL_BF16
