@@ -11,7 +11,7 @@
 // one filter per lane.  The waves share the LDS input window of the current
 // checkpoint segment.  The forward states are never stored per sample: segments
 // are visited last to first from the checkpoint taken by the forward pass; inside a
-// segment a forward sweep keeps the state at the start of every 128-sample block
+// segment a forward sweep keeps the state at the start of every level-1 block
 // (LDS), each block is re-swept keeping the state at every 16-sample sub-block
 // (registers), and each sub-block is recomputed into registers and walked backward.
 //
@@ -33,9 +33,12 @@
 namespace spiir {
 namespace {
 
-constexpr int kAdjBlk = 128;          // level-1 block (states in LDS)
+// Level-1 block (states in LDS): 128 samples, or 256 for checkpoint strides of 2048 and
+// more, where the LDS of 128-sample block states would leave three workgroups per
+// compute unit (differentiation workload: backward 1.26 -> 1.13 ms; at a stride of 512
+// the longer blocks' extra registers cost more than they save).
+__host__ __device__ constexpr int adj_block(int32_t stride) { return stride >= 2048 ? 256 : 128; }
 constexpr int kAdjSub = 16;           // level-2 sub-block (states in registers)
-constexpr int kAdjSubs = kAdjBlk / kAdjSub;
 
 struct Cx {
     float r, i;
@@ -49,7 +52,7 @@ __device__ __forceinline__ Cx step(Cx y, float ar, float ai, float br, float bi,
 // and writes the gradients.  SPLIT = true: one workgroup per (slice, segment,
 // detector) = (blockIdx.x, blockIdx.y, blockIdx.z) writes its six partial sums to
 // `part` ([det][seg][6][lanes]) for join_kernel.
-template <bool SPLIT>
+template <bool SPLIT, int BLK>
 __global__ __launch_bounds__(512) void backward_kernel(
     const float2 *__restrict__ ca, const float2 *__restrict__ cb, const int32_t *__restrict__ cd,
     const int32_t *__restrict__ perm, const Slice *__restrict__ slices, int64_t lanes_total,
@@ -61,7 +64,8 @@ __global__ __launch_bounds__(512) void backward_kernel(
     float *win = smem;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int nblk_max = stride / kAdjBlk;
+    constexpr int kSubs = BLK / kAdjSub;
+    const int nblk_max = (stride + BLK - 1) / BLK;
     float2 *c1 = reinterpret_cast<float2 *>(smem + win_floats) + (int64_t)wave * nblk_max * kWave;
     const Slice sl = slices[blockIdx.x];
     const bool active = wave < sl.n_slots;
@@ -100,27 +104,27 @@ __global__ __launch_bounds__(512) void backward_kernel(
             }
             __syncthreads();
             if (!active) continue;
-            // level 1: states entering each 128-sample block of the segment
+            // level 1: states entering each BLK-sample block of the segment
             const float2 y0 = ckpt[((int64_t)det * n_seg + seg) * lanes_total + g];
             Cx y{y0.x, y0.y};
-            const int nblk = (len + kAdjBlk - 1) / kAdjBlk;
+            const int nblk = (len + BLK - 1) / BLK;
             for (int blk = 0; blk < nblk; ++blk) {
                 c1[blk * kWave + lane] = make_float2(y.r, y.i);
-                const int e = min(kAdjBlk, len - blk * kAdjBlk);
-                const float *xp = win + base + blk * kAdjBlk;
+                const int e = min(BLK, len - blk * BLK);
+                const float *xp = win + base + blk * BLK;
                 for (int i = 0; i < e; ++i) y = step(y, ar, ai, br, bi, xp[i]);
             }
             for (int blk = nblk - 1; blk >= 0; --blk) {
-                const int b0 = blk * kAdjBlk;
-                const int e = min(kAdjBlk, len - b0);
+                const int b0 = blk * BLK;
+                const int e = min(BLK, len - b0);
                 const int nsub = (e + kAdjSub - 1) / kAdjSub;
                 // level 2: states entering each 16-sample sub-block of the block
-                Cx c2[kAdjSubs];
+                Cx c2[kSubs];
                 {
                     const float2 cb1 = c1[blk * kWave + lane];
                     Cx yy{cb1.x, cb1.y};
 #pragma unroll
-                    for (int sb = 0; sb < kAdjSubs; ++sb) {
+                    for (int sb = 0; sb < kSubs; ++sb) {
                         c2[sb] = yy;
                         if (sb < nsub) {
                             const int f = min(kAdjSub, e - sb * kAdjSub);
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(512) void backward_kernel(
                     }
                 }
 #pragma unroll
-                for (int sb = kAdjSubs - 1; sb >= 0; --sb) {
+                for (int sb = kSubs - 1; sb >= 0; --sb) {
                     if (sb >= nsub) continue;
                     const int f = min(kAdjSub, e - sb * kAdjSub);
                     const int q0 = b0 + sb * kAdjSub;   // segment offset of the sub-block
@@ -242,17 +246,45 @@ __global__ void join_kernel(const float2 *__restrict__ part, const int32_t *__re
 size_t backward_lds_bytes(int32_t stride, int32_t hist_len, int32_t fpl) {
     const int32_t win_floats = ((stride + hist_len + kSub) + 3) & ~3;
     return (size_t)win_floats * sizeof(float) +
-           (size_t)fpl * (stride / kAdjBlk) * kWave * sizeof(float2);
+           (size_t)fpl * ((stride + adj_block(stride) - 1) / adj_block(stride)) * kWave *
+               sizeof(float2);
 }
 
 hipError_t prepare_backward(const Bank &bk) {
     const int lds = (int)backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl);
-    hipError_t e = hipFuncSetAttribute((const void *)backward_kernel<false>,
+    const bool longb = adj_block(bk.ckpt_stride) == 256;
+    hipError_t e = hipFuncSetAttribute(longb ? (const void *)backward_kernel<false, 256>
+                                             : (const void *)backward_kernel<false, 128>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)backward_kernel<true>,
+    return hipFuncSetAttribute(longb ? (const void *)backward_kernel<true, 256>
+                                     : (const void *)backward_kernel<true, 128>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
+
+namespace {
+
+template <int BLK>
+void launch_backward_blk(const Bank &bk, const float *x, int32_t n, const float2 *gz,
+                         const float2 *ckpt, float2 *grad_a, float2 *grad_b, int32_t n_seg,
+                         int32_t win_floats, int64_t lanes, size_t lds, hipStream_t s) {
+    if (n_seg > 1 && bk.d_bwd_part != nullptr && n_seg <= bk.bwd_max_seg) {
+        hipLaunchKernelGGL((backward_kernel<true, BLK>), dim3(bk.n_slices, n_seg, bk.n_det),
+                           dim3(kWave * bk.fpl), lds, s, bk.d_a, bk.d_b, bk.d_delay, bk.d_perm,
+                           bk.d_slices, lanes, x, n, bk.n_det, bk.hist_len, gz, bk.n_templates, ckpt,
+                           bk.ckpt_stride, n_seg, grad_a, grad_b, win_floats, bk.d_bwd_part);
+        const int64_t blocks = std::min<int64_t>((lanes + 255) / 256, 8192);
+        hipLaunchKernelGGL(join_kernel, dim3((unsigned)blocks), dim3(256), 0, s, bk.d_bwd_part,
+                           bk.d_perm, lanes, bk.n_det, n_seg, grad_a, grad_b);
+    } else {
+        hipLaunchKernelGGL((backward_kernel<false, BLK>), dim3(bk.n_slices), dim3(kWave * bk.fpl),
+                           lds, s, bk.d_a, bk.d_b, bk.d_delay, bk.d_perm, bk.d_slices, lanes, x,
+                           n, bk.n_det, bk.hist_len, gz, bk.n_templates, ckpt, bk.ckpt_stride,
+                           n_seg, grad_a, grad_b, win_floats, nullptr);
+    }
+}
+
+}  // namespace
 
 hipError_t launch_backward(const Bank &bk, const float *x, int32_t n, const float2 *gz,
                            const float2 *ckpt, float2 *grad_a, float2 *grad_b, hipStream_t s) {
@@ -262,20 +294,10 @@ hipError_t launch_backward(const Bank &bk, const float *x, int32_t n, const floa
     const int32_t win_floats = ((bk.ckpt_stride + bk.hist_len + kSub) + 3) & ~3;
     const int64_t lanes = bk.n_slots * kWave;
     const size_t lds = backward_lds_bytes(bk.ckpt_stride, bk.hist_len, bk.fpl);
-    if (n_seg > 1 && bk.d_bwd_part != nullptr && n_seg <= bk.bwd_max_seg) {
-        hipLaunchKernelGGL(backward_kernel<true>, dim3(bk.n_slices, n_seg, bk.n_det),
-                           dim3(kWave * bk.fpl), lds, s, bk.d_a, bk.d_b, bk.d_delay, bk.d_perm,
-                           bk.d_slices, lanes, x, n, bk.n_det, bk.hist_len, gz, bk.n_templates, ckpt,
-                           bk.ckpt_stride, n_seg, grad_a, grad_b, win_floats, bk.d_bwd_part);
-        const int64_t blocks = std::min<int64_t>((lanes + 255) / 256, 8192);
-        hipLaunchKernelGGL(join_kernel, dim3((unsigned)blocks), dim3(256), 0, s, bk.d_bwd_part,
-                           bk.d_perm, lanes, bk.n_det, n_seg, grad_a, grad_b);
-    } else {
-        hipLaunchKernelGGL(backward_kernel<false>, dim3(bk.n_slices), dim3(kWave * bk.fpl), lds, s,
-                           bk.d_a, bk.d_b, bk.d_delay, bk.d_perm, bk.d_slices, lanes, x, n,
-                           bk.n_det, bk.hist_len, gz, bk.n_templates, ckpt, bk.ckpt_stride, n_seg,
-                           grad_a, grad_b, win_floats, nullptr);
-    }
+    if (adj_block(bk.ckpt_stride) == 256)
+        launch_backward_blk<256>(bk, x, n, gz, ckpt, grad_a, grad_b, n_seg, win_floats, lanes, lds, s);
+    else
+        launch_backward_blk<128>(bk, x, n, gz, ckpt, grad_a, grad_b, n_seg, win_floats, lanes, lds, s);
     return hipGetLastError();
 }
 
