@@ -26,8 +26,11 @@ def per_template_rel(g, g_ref, offsets):
     return np.array(out)
 
 
+# strides of 2048 and more keep block states every 256 samples: 2176 and 4480 end their
+# segments with a 128-sample block
 @pytest.mark.parametrize("stride, n, balance_wgs", [(128, 1000, 0), (2048, 3000, 0), (256, 256, 0),
-                                                  (4096, 4000, 0), (128, 3000, 2)])
+                                                  (4096, 4000, 0), (128, 3000, 2),
+                                                  (2176, 4352, 0), (4480, 5000, 2)])
 def test_backward_matches_oracle_gradient(gpu, stride, n, balance_wgs):
     import torch
     rng = np.random.default_rng(stride + n)
