@@ -70,8 +70,9 @@ typedef struct {
                                  (multiple of 16): the persistent work-queue scan with
                                  packets cut into time tiles of this many samples */
     int32_t block_len;        /* block form: time-block length L, 64, 128 or 256; 0 = 128 */
-    double long_pole_abs_a;   /* block form: filters with |a_k| above this carry their
-                                 block-to-block state in FP64; <= 0 = 0.999 */
+    double long_pole_abs_a;   /* block form: a tile of 16 filters (of one template) carries
+                                 its block-to-block state in FP64 when any of them has
+                                 |a_k| above this, in FP32 otherwise; <= 0 = 0.999 */
     int32_t ckpt_stride;      /* differentiation: samples per checkpoint segment,
                                  a multiple of 128; 0 = 2048 */
     int32_t balance_wgs;      /* FP32 scan with time_tile -1 or 0: 0 = one wave per filter
@@ -137,8 +138,8 @@ typedef struct {
     int32_t time_tile;        /* 0 when the scan is not time-split */
     int32_t scan_waves;       /* grid of the persistent scan */
     int32_t block_len;
-    int32_t n_long_pole;      /* block form: filters carried in FP64 (counted from the
-                                 coefficients given at creation) */
+    int32_t n_long_pole;      /* block form: filters with |a_k| above long_pole_abs_a
+                                 (counted from the coefficients given at creation) */
     int32_t scan_wait_timeouts; /* state hand-off waits (persistent or balanced scan) that hit their
                                    bound since creation or the last reset: the stream's results
                                    from that packet on are invalid; 0 normally */

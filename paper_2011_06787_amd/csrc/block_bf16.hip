@@ -12,8 +12,9 @@
 //   kernel 1 (split_input)   x -> bf16 hi + lo planes (x = hi + lo to ~2^-17)
 //   kernel 2 (block_state)   S = W'.H per 16 delay-sorted filters of a template (the
 //                            operand W' holds b a^{L-1-i} on the band sigma = i - d_k),
-//                            then the block-to-block carry (FP64 where |a| > 0.999,
-//                            FP32 otherwise, a^L in FP64), writing Y as bf16 hi + lo
+//                            then the block-to-block carry (FP64 for tiles holding a
+//                            filter with |a| > 0.999, FP32 otherwise, a^L in FP64),
+//                            writing Y as bf16 hi + lo
 //   kernel 3 (block_output)  z_t = [P_t | M_t] [Y_t ; H], P_t[j,k] = a_k^{j+1}
 // Every product runs as hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16 with FP32
 // accumulation.  Complex operands use the real 2x2 block form; output rows are
@@ -71,7 +72,8 @@ __global__ void split_input_kernel(const float *__restrict__ x, int32_t n,
 // group's total, the four group totals are combined through LDS (Ystart[q+1] = A^len
 // Ystart[q] + T[q]), and each lane then runs its group again from Ystart[q], writing the
 // state entering every block as bf16 hi + lo (running the group twice keeps no
-// per-block state in registers).  R is double for long-pole filters, float otherwise.
+// per-block state in registers).  R is double for tiles with a long-pole filter, float
+// otherwise.
 // AG = A^kGroup (precomputed per filter).
 constexpr int kChunk = 64;
 constexpr int kGroup = kChunk / 4;
@@ -212,7 +214,10 @@ __global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
     const int q = lane >> 4;
     const int64_t gf = tl.g0 + f;
     const double2 ta = active ? aL[gf] : make_double2(0.0, 0.0);
-    const bool long_pole = active && lp[gf] != 0;
+    // The carry's precision is chosen per tile, for the whole wave: FP64 when any of the
+    // tile's 16 filters has |a| above the long-pole threshold.  A per-filter choice made
+    // every wave holding both kinds run both carries and both sets of state stores.
+    const bool long_pole = __builtin_amdgcn_ballot_w64(active && lp[gf] != 0) != 0;
     const C2<double> A64{ta.x, ta.y};
     const C2<float> A32{(float)ta.x, (float)ta.y};
     C2<double> AG64{1.0, 0.0};

@@ -2,7 +2,8 @@
 
 Tolerance: relative SNR error per (detector, template) at most 1e-3 for the
 split-bf16 block form (the products run as hi*hi + hi*lo + lo*hi in bf16 with
-FP32 accumulation, the block-to-block carry in FP64 for |a| > 0.999).
+FP32 accumulation, the block-to-block carry in FP64 for every tile of 16 filters
+holding one with |a| > 0.999).
 """
 import numpy as np
 import pytest
@@ -71,6 +72,24 @@ def test_long_pole_carry_in_fp64(gpu):
     assert info.n_long_pole == int(np.sum(np.abs(bank.a.astype(np.complex128)) > 0.999))
     assert info.n_long_pole > 0
     assert oracle.rel_err(z, z_ref).max() <= TOL_BF16
+
+
+@pytest.mark.parametrize("threshold", [0.5, 0.999, 0.99985, 0.9999999])
+def test_carry_precision_is_chosen_per_tile(gpu, threshold):
+    """Memory times log-uniform in [5 ms, 4 s] put filters on both sides of every threshold
+    in most tiles of 16: every tile carries in FP64 (0.5, 0.999), most tiles in FP32 and
+    the others in FP64 (0.99985: 9 of the 316 filters above it), or every tile in FP32
+    (0.9999999: above the largest |a|); each within the tolerance."""
+    rng = np.random.default_rng(1250)
+    bank = synth.draw_filters(rng, np.array([40, 9, 170, 33, 64]))
+    x = rng.standard_normal((2, 8192)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    z, _, _, info = run_block(gpu, bank, x, 4096, long_pole=threshold)
+    absa = np.abs(bank.a.astype(np.complex128))
+    assert info.n_long_pole == int(np.sum(absa > threshold))
+    err = oracle.rel_err(z, z_ref).max()
+    print(f"threshold {threshold}: {info.n_long_pole} long-pole filters, max rel err {err:.3e}")
+    assert err <= TOL_BF16
 
 
 def test_block_form_empty_template_and_zero_delay(gpu):
