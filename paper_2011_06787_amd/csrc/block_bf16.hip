@@ -148,6 +148,39 @@ __device__ __forceinline__ void carry_chunk(const float (*sl)[kChunk + 1], C2<R>
     }
 }
 
+// s_waitcnt with vmcnt = N and lgkmcnt = 0 (gfx9 encoding: vmcnt in bits 3:0 and
+// 15:14, expcnt 6:4 left at its maximum, lgkmcnt 11:8)
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+// 16-byte LDS read at byte address `addr` (+ imm); the result is tied to an
+// explicit lgkmcnt wait by the caller
+template <int OFF>
+__device__ __forceinline__ bf16x8 lds_read16(uint32_t addr) {
+    bf16x8 v;
+    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
+    return v;
+}
+
+// LDS (address space 3) pointer to element `elem` of `smem`, and its byte address
+__device__ __forceinline__ __attribute__((address_space(3))) void *lds_elem(uint16_t *smem, int elem) {
+    return (__attribute__((address_space(3))) void *)(
+        (__attribute__((address_space(3))) uint16_t *)smem + elem);
+}
+
+// direct global-to-LDS load of 16 bytes per lane: lane i's bytes from `src` land at
+// element `elem` of `smem` (wave-uniform) + 16 x i bytes
+__device__ __forceinline__ void lds_dma16(const void *src, uint16_t *smem, int elem) {
+    __builtin_amdgcn_global_load_lds(src, lds_elem(smem, elem), 16, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t lds_byte_addr(uint16_t *smem) {
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint16_t *)smem;
+}
+
 // One workgroup of kStateWaves waves per kStateWaves consecutive tiles; wave w owns
 // tile blockIdx.x*kStateWaves + w (16 filters) for every detector in turn.  The
 // tile's W' fragments of its first kACache K steps (nearly every tile has fewer than
@@ -241,11 +274,26 @@ __global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
             const int span = (cols - 1) * L + (p_hi - p_lo);   // multiple of 16
             const int64_t g0 = (int64_t)c0 * L + p_lo;
             __syncthreads();   // previous chunk's S rows no longer read
-            for (int e = threadIdx.x; e < span / 8 * 2; e += blockDim.x) {
-                const int plane = e & 1;
-                const int pp = (e >> 1) * 8;
-                const bf16x8 v = load8((plane ? xl : xh) + g0 + pp);
-                *reinterpret_cast<bf16x8 *>((plane ? slo : sh) + skew(pp, L)) = v;
+            {
+                // 16-byte unit u of the range goes to slot u + u / R of its plane (R units
+                // per row of L, then the skew's one-unit gap); the slots are filled by
+                // direct global-to-LDS loads, 64 consecutive slots per instruction, all in
+                // flight together.  A gap slot takes a copy of its row's last unit (an
+                // in-range address) and is never read.
+                const int R = L / 8;
+                const int U = span / 8;
+                const int slots = U + (U - 1) / R;
+                const int n_ins = (slots + kWave - 1) / kWave;
+                for (int k = wave; k < 2 * n_ins; k += kStateWaves) {
+                    const int plane = k >= n_ins;
+                    const int s0 = (k - plane * n_ins) * kWave;
+                    const int sl_ = s0 + lane;
+                    const int row = sl_ / (R + 1), w = sl_ % (R + 1);
+                    const int u = row * R + min(w, R - 1);
+                    if (sl_ < slots)
+                        lds_dma16((plane ? xl : xh) + g0 + 8 * u, plane ? slo : sh, 8 * s0);
+                }
+                wait_vm_lgkm0<0>();
             }
             __syncthreads();
             f32x16 acc[2] = {};
@@ -332,39 +380,6 @@ __host__ __device__ constexpr int out_stage_elems(int rw) {
 }
 
 size_t block_output_lds_bytes(int rw) { return (size_t)kStages * out_stage_elems(rw) * sizeof(uint16_t); }
-
-// s_waitcnt with vmcnt = N and lgkmcnt = 0 (gfx9 encoding: vmcnt in bits 3:0 and
-// 15:14, expcnt 6:4 left at its maximum, lgkmcnt 11:8)
-template <int N>
-__device__ __forceinline__ void wait_vm_lgkm0() {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
-}
-
-// 16-byte LDS read at byte address `addr` (+ imm); the result is tied to an
-// explicit lgkmcnt wait by the caller
-template <int OFF>
-__device__ __forceinline__ bf16x8 lds_read16(uint32_t addr) {
-    bf16x8 v;
-    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
-    return v;
-}
-
-// LDS (address space 3) pointer to element `elem` of `smem`, and its byte address
-__device__ __forceinline__ __attribute__((address_space(3))) void *lds_elem(uint16_t *smem, int elem) {
-    return (__attribute__((address_space(3))) void *)(
-        (__attribute__((address_space(3))) uint16_t *)smem + elem);
-}
-
-// direct global-to-LDS load of 16 bytes per lane: lane i's bytes from `src` land at
-// element `elem` of `smem` (wave-uniform) + 16 x i bytes
-__device__ __forceinline__ void lds_dma16(const void *src, uint16_t *smem, int elem) {
-    __builtin_amdgcn_global_load_lds(src, lds_elem(smem, elem), 16, 0, 0);
-}
-
-__device__ __forceinline__ uint32_t lds_byte_addr(uint16_t *smem) {
-    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint16_t *)smem;
-}
 
 // lgkmcnt wait that the MFMAs reading a and b cannot be moved above
 template <int N>
