@@ -381,10 +381,14 @@ __host__ __device__ constexpr int out_stage_elems(int rw) {
 
 size_t block_output_lds_bytes(int rw) { return (size_t)kStages * out_stage_elems(rw) * sizeof(uint16_t); }
 
-// lgkmcnt wait that the MFMAs reading a and b cannot be moved above
-template <int N>
-__device__ __forceinline__ void wait_lgkm(bf16x8 &a, bf16x8 &b) {
-    asm volatile("s_waitcnt lgkmcnt(%2)" : "+v"(a), "+v"(b) : "i"(N));
+// wait for every LDS read of the step, which the MFMAs reading the fragments cannot be
+// moved above
+__device__ __forceinline__ void wait_frags(bf16x8 &a0, bf16x8 &a1, bf16x8 &a2, bf16x8 &a3,
+                                           bf16x8 &b0, bf16x8 &b1, bf16x8 &b2, bf16x8 &b3,
+                                           bf16x8 &b4, bf16x8 &b5, bf16x8 &b6, bf16x8 &b7) {
+    asm volatile("s_waitcnt lgkmcnt(0)"
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(b0), "+v"(b1), "+v"(b2),
+                   "+v"(b3), "+v"(b4), "+v"(b5), "+v"(b6), "+v"(b7));
 }
 
 template <int RW>
@@ -489,18 +493,15 @@ __global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_k
         bf16x8 bh1 = lds_read16<1024>(pb), bl1 = lds_read16<kPl + 1024>(pb);
         bf16x8 bh2 = lds_read16<2048>(pb), bl2 = lds_read16<kPl + 2048>(pb);
         bf16x8 bh3 = lds_read16<3072>(pb), bl3 = lds_read16<kPl + 3072>(pb);
-        wait_lgkm<6>(ah0, al0);
-        wait_lgkm<6>(ah1, al1);
-        wait_lgkm<6>(bh0, bl0);
+        // one wait for all twelve reads: waiting for the first fragments only, and
+        // starting on them, measured no faster
+        wait_frags(ah0, al0, ah1, al1, bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3);
         acc[0][0] = mma3(ah0, al0, bh0, bl0, acc[0][0]);
         acc[1][0] = mma3(ah1, al1, bh0, bl0, acc[1][0]);
-        wait_lgkm<4>(bh1, bl1);
         acc[0][1] = mma3(ah0, al0, bh1, bl1, acc[0][1]);
         acc[1][1] = mma3(ah1, al1, bh1, bl1, acc[1][1]);
-        wait_lgkm<2>(bh2, bl2);
         acc[0][2] = mma3(ah0, al0, bh2, bl2, acc[0][2]);
         acc[1][2] = mma3(ah1, al1, bh2, bl2, acc[1][2]);
-        wait_lgkm<0>(bh3, bl3);
         acc[0][3] = mma3(ah0, al0, bh3, bl3, acc[0][3]);
         acc[1][3] = mma3(ah1, al1, bh3, bl3, acc[1][3]);
     }
