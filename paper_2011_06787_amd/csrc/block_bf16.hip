@@ -183,9 +183,9 @@ __device__ __forceinline__ uint32_t lds_byte_addr(uint16_t *smem) {
 
 // One workgroup of kStateWaves waves per kStateWaves consecutive tiles; wave w owns
 // tile blockIdx.x*kStateWaves + w (16 filters) for every detector in turn.  The
-// tile's W' fragments of its first kACache K steps (nearly every tile has fewer than
-// that) are loaded into registers once and serve every chunk of every detector;
-// further steps stream from memory.  For every chunk of kChunk blocks the workgroup
+// tile's W' fragments of its first kACache K steps are loaded into registers once and
+// serve every chunk of every detector; further steps (a tile of the precision bank has
+// 11-16 at L = 128) are read again from memory for every chunk.  For every chunk of kChunk blocks the workgroup
 // stages the input range all its tiles read,
 //     x[c0 L + P_lo, (c0 + kChunk - 1) L + P_hi)     (P_lo, P_hi: union band of the tiles)
 // once into LDS (hi and lo planes), skewed by 8 elements per row of L so that the
@@ -196,11 +196,14 @@ __device__ __forceinline__ uint32_t lds_byte_addr(uint16_t *smem) {
 // two uses and several workgroups share a CU.
 constexpr int kStateWaves = 4;
 constexpr int kSlFloats = 32 * (kChunk + 1);   // one wave's S rows
-constexpr int kACache = 4;                    // W' K steps kept in registers
+// W' K steps kept in registers: with the two-pass carry, 8 of them fit the 168-register
+// budget of three waves per SIMD (4: 11.72-11.76 ms per precision pass, 8: 11.54-11.63)
+constexpr int kACache = 8;
 
 __device__ __forceinline__ int skew(int p, int L) { return p + 8 * (p / L); }
 
-__global__ __launch_bounds__(kWave *kStateWaves) void block_state_kernel(
+__global__ __launch_bounds__(kWave *kStateWaves) __attribute__((amdgpu_waves_per_eu(3)))
+void block_state_kernel(
     const WTile *__restrict__ tiles, int32_t n_tiles, const BTemplate *__restrict__ tmpls,
     const uint16_t *__restrict__ wa, const uint16_t *__restrict__ xs, int64_t xs_stride,
     int32_t hist_pad, int32_t n_det, int32_t L, int32_t nb, const double2 *__restrict__ aL,
