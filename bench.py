@@ -32,6 +32,7 @@ FLOP_PER_UPDATE = 12          # Section II.B.2
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 peak: 256 CU x 4 SIMD x 32 lanes x 2 flop x 2.4 GHz
 VALU_OPS_PER_UPDATE = 8       # 2 mul + 4 fma + 2 lane-sum adds carry the 12 flop of an update
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense bf16 matrix-core peak
 
 
 def log(msg):
@@ -281,6 +282,15 @@ def precision_comparison(args, dev):
                      "templates_checked": len(pick), "argmax": amx,
                      "create_s": t_create, "device_bytes": info.device_bytes,
                      "long_pole_filters": info.n_long_pole}
+        if kw["mode"] == spiir.MODE_BF16_BLOCK and launches:
+            # both matrix-core products of the pass (three split products each) over the
+            # whole pass time on the bank's stream, against the dense bf16 peak
+            flop = info.block_mfma_flop_per_column * D * (N // kw["block_len"])
+            achieved = flop / (kern_ms / launches * 1e-3) / 1e12
+            out[name]["mfma"] = {"flop_per_pass": flop, "achieved": achieved,
+                                 "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": achieved / PEAK_BF16_TFLOPS,
+                                 "over": "whole pass (split, state, output kernels)"}
         log(f"precision {name}: {wall * 1e3:.2f} ms/pass, {F * D * N / wall:.4g} upd/s, "
             f"rel err max {err.max():.2e}, argmax {amx['equal_under_clear_margin']}/"
             f"{amx['clear_margin']} equal where clear, {amx['ambiguous']} ambiguous, "

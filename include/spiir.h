@@ -145,6 +145,10 @@ typedef struct {
                                    from that packet on are invalid; 0 normally */
     int32_t balance_waves;    /* waves per detector of the balanced schedule; 0 when the
                                  scan does not use it */
+    int64_t block_mfma_flop_per_column; /* block form: matrix-core flop of its two products
+                                 (input-to-state and output, three split products each)
+                                 per column, i.e. per detector and block of L samples;
+                                 0 for the FP32 scan */
 } spiir_bank_info;
 
 /* Fill `info`.  Waits for the bank's last stream (to read the wait-timeout count). */

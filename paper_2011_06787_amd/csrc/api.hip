@@ -627,6 +627,7 @@ spiir_status spiir_bank_get_info(const spiir_bank *h, spiir_bank_info *info) {
     info->balance_waves = bk.balanced ? bk.balance_waves : 0;
     info->block_len = bk.block_len;
     info->n_long_pole = bk.n_long_pole;
+    info->block_mfma_flop_per_column = bk.mode == SPIIR_MODE_BF16_BLOCK ? bk.block_flop_per_col : 0;
     if (bk.d_queue != nullptr) {
         spiir::ScanQueue q{};
         SPIIR_HIP(hipStreamSynchronize(bk.last_stream));

@@ -253,6 +253,9 @@ spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const 
     for (size_t i = 0; i < tiles.size(); ++i)
         for (int32_t ks = 0; ks < tiles[i].nks; ++ks) wblk[(size_t)(tiles[i].a_off / 1024 + ks)] = (int32_t)i;
     bk.n_wblocks = waoff / 1024;
+    // every operand block (32 rows x 16 K entries, hi and lo planes) takes part in three
+    // 32x32x16 products per 32 columns: 32 x 16 x 2 x 3 flop per column
+    bk.block_flop_per_col = (waoff / 1024 + aoff / 1024) * (32 * 16 * 2 * 3);
     int32_t pmax = 0, mmax = 0;
     for (const BTemplate &bt : tm) {
         pmax = std::max(pmax, bt.nks_p * rt_per);

@@ -152,6 +152,7 @@ struct Bank {
     int32_t *d_gd = nullptr;     // [n_fpad] delays in sorted-padded order (padding: past every band)
     int32_t *d_wblk = nullptr;   // [n_wblocks] tile of every input-to-state operand block
     int64_t n_wblocks = 0;
+    int64_t block_flop_per_col = 0;   // matrix-core flop of both products per column
     int32_t max_p_blocks = 0;    // output-operand blocks of the largest template: state part
     int32_t max_m_blocks = 0;    // and input part
 

@@ -69,6 +69,7 @@ class BankInfo(ctypes.Structure):
         ("time_tile", ctypes.c_int32), ("scan_waves", ctypes.c_int32),
         ("block_len", ctypes.c_int32), ("n_long_pole", ctypes.c_int32),
         ("scan_wait_timeouts", ctypes.c_int32), ("balance_waves", ctypes.c_int32),
+        ("block_mfma_flop_per_column", ctypes.c_int64),
     ]
 
 

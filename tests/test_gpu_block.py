@@ -176,3 +176,17 @@ def test_block_form_is_deterministic_across_detectors_and_chunks(gpu, block_len)
     assert torch.equal(zs[0], zs[1])
     err = oracle.rel_err(zs[0].cpu().numpy(), oracle.filter(bank, x.cpu().numpy()))
     assert err.max() <= TOL_BF16
+
+
+def test_matrix_core_work_reported_per_column(gpu):
+    """One template of 16 filters with zero delays at L = 64: the input-to-state operand is
+    one tile of 4 K steps (offsets 0..63), the output operand 4 row tiles x (2 state + 4
+    input K steps); each 32x16 operand block makes 3 split products of 32 x 16 x 2 flop per
+    column.  The FP32 scan reports none."""
+    rng = np.random.default_rng(1500)
+    bank = synth.draw_filters(rng, np.array([16]), max_delay=0)
+    with gpu.SpiirBank.from_bank(bank, max_chunk=1024, mode=gpu.MODE_BF16_BLOCK,
+                                 block_len=64) as sb:
+        assert sb.info.block_mfma_flop_per_column == (4 + 4 * (2 + 4)) * 32 * 16 * 2 * 3
+    with gpu.SpiirBank.from_bank(bank, max_chunk=1024) as sb:
+        assert sb.info.block_mfma_flop_per_column == 0
