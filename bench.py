@@ -154,6 +154,8 @@ def parse():
     p.add_argument("--no-check", action="store_true")
     p.add_argument("--cpu-templates", type=int, default=1024,
                    help="templates in the oracle's timed sample (full 64-s stream)")
+    p.add_argument("--no-tiny", action="store_true",
+                   help="skip the tiny workload (parity and per-packet latency)")
     p.add_argument("--no-precision", action="store_true",
                    help="skip the split-bf16 block form vs FP32 scan comparison")
     p.add_argument("--precision-only", action="store_true")
@@ -312,6 +314,71 @@ def multi_group_slices(bank, fpl):
     counts = np.diff(bank.offsets.astype(np.int64))
     groups = ((counts + 63) // 64 + fpl - 1) // fpl
     return int(groups[groups > 1].sum())
+
+
+def tiny_run(args, dev):
+    """Tiny workload (4 templates x 128 filters, one detector, 8 s): parity over the whole
+    stream and per-packet latency of 1-s packets, the launch-bound end of the path (512
+    filters cannot fill the chip), in the schedule the autotuner picks for it.  Latency
+    per packet: host wall time of filter_chunk plus a synchronisation, and the filtering
+    kernels' time from HIP events on the bank's stream."""
+    import torch
+    import oracle
+    from paper_2011_06787_amd import spiir
+    w = synth.tiny()
+    bank, x_host = w.bank, w.input()
+    D, N = x_host.shape
+    T = bank.n_templates
+    chunk = 2048
+    z_ref = oracle.filter(bank, x_host)
+    x = torch.from_numpy(x_host).to(dev)
+    packets = [x[:, i:i + chunk].contiguous() for i in range(0, N, chunk)]
+    mode, opts, tuned = spiir.MODE_FP32_SCAN, {}, None
+    if not args.no_tune:
+        # the latency-optimal schedule for this size (every FP32 schedule and block length)
+        from paper_2011_06787_amd import tune
+        best, trials = tune.autotune(bank, packets[:2], reps=20)
+        mode, opts = best.mode, dict(best.opts)
+        tuned = {"chosen": {"mode": mode, **opts},
+                 "trials": [{"mode": t.mode, **t.opts, "ms_per_packet": t.ms_per_packet}
+                            for t in trials]}
+    sb = spiir.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=chunk, mode=mode, **opts)
+    z = torch.empty((D, T, chunk), dtype=torch.complex64, device=dev)
+    pk = torch.empty((D, T, 1), dtype=torch.float32, device=dev)
+    am = torch.empty((D, T, 1), dtype=torch.int32, device=dev)
+    zs, pks, ams = [], [], []
+    for xp in packets:                              # one pass over the stream, checked
+        sb.filter_chunk(xp, z, pk, am)
+        zs.append(z.cpu().numpy()); pks.append(pk.cpu().numpy()); ams.append(am.cpu().numpy())
+    z_all = np.concatenate(zs, axis=-1)
+    err = oracle.rel_err(z_all, z_ref)
+    amx = argmax_report(np.concatenate(pks, axis=-1), np.concatenate(ams, axis=-1), z_all,
+                        z_ref, chunk)
+    reps = 200
+    sb.reset()
+    torch.cuda.synchronize()
+    sb.set_timing(True, capacity=reps)
+    wall = []
+    for i in range(reps):
+        t0 = time.perf_counter()
+        sb.filter_chunk(packets[i % len(packets)], z, pk, am)
+        torch.cuda.synchronize()
+        wall.append((time.perf_counter() - t0) * 1e3)
+    kern_ms, launches = sb.kernel_time()
+    info = sb.refresh_info()
+    sb.close()
+    wall = np.asarray(wall[10:])
+    out = {"workload": "tiny: 4 templates x 128 filters, 1 detector, 8 s at 2048 Hz in 1-s packets",
+           "packets_timed": int(wall.size),
+           "packet_latency_ms": {"p50": float(np.percentile(wall, 50)),
+                                 "p99": float(np.percentile(wall, 99))},
+           "kernel_ms": kern_ms / max(launches, 1),
+           "rel_err_max": float(err.max()), "templates_checked": T, "argmax": amx,
+           "wait_timeouts": info.scan_wait_timeouts, "mode": mode, "options": opts,
+           "autotune": tuned}
+    log(f"tiny: packet p50 {out['packet_latency_ms']['p50']:.3f} ms (kernels "
+        f"{out['kernel_ms'] * 1e3:.1f} us, mode {mode} {opts}), rel err max {err.max():.2e}")
+    return out
 
 
 def batching_run(args, dev):
@@ -864,6 +931,8 @@ def main():
     sb.close()
     del sb
     torch.cuda.empty_cache()
+    if not args.no_tiny:
+        result["tiny"] = tiny_run(args, dev)
     if not args.no_precision:
         result["precision"] = precision_comparison(args, dev)
     if not args.no_batching:
