@@ -64,7 +64,7 @@ typedef struct {
     int32_t peak_window;      /* samples per peak window of spiir_filter_chunk;
                                  0 = one window per packet */
     int32_t mode;             /* spiir_mode */
-    int32_t filters_per_lane; /* FP32 scan: filters held per GPU lane, 2, 4 or 8; 0 = 4 */
+    int32_t filters_per_lane; /* FP32 scan: filters held per GPU lane, 1, 2, 4 or 8; 0 = 4 */
     int32_t time_tile;        /* FP32 scan schedule.  -1 or 0: one wave per filter group
                                  walks the whole packet (see balance_wgs).  16..4096
                                  (multiple of 16): the persistent work-queue scan with

@@ -407,8 +407,8 @@ spiir_status spiir_bank_create(int32_t n_templates, const int32_t *offsets, cons
                 return fail(SPIIR_E_INVAL, "block form: peak_window must be a multiple of block_len");
         }
         int fpl = opts.filters_per_lane == 0 ? 4 : opts.filters_per_lane;
-        if (fpl != 2 && fpl != 4 && fpl != 8)
-            return fail(SPIIR_E_INVAL, "filters_per_lane must be 2, 4 or 8");
+        if (fpl != 1 && fpl != 2 && fpl != 4 && fpl != 8)
+            return fail(SPIIR_E_INVAL, "filters_per_lane must be 1, 2, 4 or 8");
         const int time_tile = opts.time_tile;
         if (time_tile != -1 && time_tile != 0 &&
             (time_tile < spiir::kSub || time_tile > 4096 || time_tile % spiir::kSub != 0))

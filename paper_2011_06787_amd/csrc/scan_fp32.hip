@@ -935,8 +935,11 @@ void launch_fpl(const Bank &bk, const float *x, int32_t n, float2 *ckpt, float2 
 
 }  // namespace
 
+// One filter per lane (groups of 64, the most waves for a small bank) runs the two-filter
+// kernels, every group holding one slot.
 hipError_t prepare_scan_fp32(Bank &bk) {
     switch (bk.fpl) {
+    case 1:
     case 2: return prepare_fpl<2>(bk);
     case 4: return prepare_fpl<4>(bk);
     case 8: return prepare_fpl<8>(bk);
@@ -956,6 +959,7 @@ hipError_t launch_scan_fp32(const Bank &bk, const float *x, int32_t n, float2 *c
                             float *peak, int32_t *argmax, hipStream_t s) {
     if (n <= 0 || bk.n_slices == 0) return hipSuccess;
     switch (bk.fpl) {
+    case 1:
     case 2: launch_fpl<2>(bk, x, n, ckpt, z, peak, argmax, s); break;
     case 4: launch_fpl<4>(bk, x, n, ckpt, z, peak, argmax, s); break;
     case 8: launch_fpl<8>(bk, x, n, ckpt, z, peak, argmax, s); break;

@@ -21,7 +21,7 @@ import numpy as np
 
 from . import spiir
 
-DEFAULT_SCAN = ([dict(filters_per_lane=f, time_tile=t) for f in (2, 4, 8) for t in (0, 512)] +
+DEFAULT_SCAN = ([dict(filters_per_lane=f, time_tile=t) for f in (1, 2, 4, 8) for t in (0, 512)] +
                 [dict(filters_per_lane=f, time_tile=0, balance_wgs=c)
                  for f, c in ((2, 4), (4, 2), (4, 3), (4, 4), (8, 2), (8, 3))])
 DEFAULT_BLOCK = [dict(block_len=L) for L in (64, 128, 256)]

@@ -28,10 +28,11 @@ def per_template_rel(g, g_ref, offsets):
 
 # strides of 2048 and more keep block states every 256 samples: 2176 and 4480 end their
 # segments with a 128-sample block
-@pytest.mark.parametrize("stride, n, balance_wgs", [(128, 1000, 0), (2048, 3000, 0), (256, 256, 0),
-                                                  (4096, 4000, 0), (128, 3000, 2),
-                                                  (2176, 4352, 0), (4480, 5000, 2)])
-def test_backward_matches_oracle_gradient(gpu, stride, n, balance_wgs):
+@pytest.mark.parametrize("stride, n, balance_wgs, fpl", [
+    (128, 1000, 0, 4), (2048, 3000, 0, 4), (256, 256, 0, 4), (4096, 4000, 0, 4), (128, 3000, 2, 4),
+    (2176, 4352, 0, 4), (4480, 5000, 2, 4), (512, 2000, 0, 1), (2048, 2500, 2, 1),
+    (1024, 3000, 0, 8)])
+def test_backward_matches_oracle_gradient(gpu, stride, n, balance_wgs, fpl):
     import torch
     rng = np.random.default_rng(stride + n)
     bank = synth.draw_filters(rng, np.array([64, 100, 7, 256]), max_delay=500)
@@ -43,7 +44,7 @@ def test_backward_matches_oracle_gradient(gpu, stride, n, balance_wgs):
     gz = (2 * z_ref + w).astype(np.complex64)         # dL/dz of L = sum |z|^2 + Re sum conj(w) z
     ga_ref, gb_ref = oracle.grad(bank, x, gz)
     with gpu.SpiirBank.from_bank(bank, n_detectors=D, max_chunk=n, ckpt_stride=stride,
-                                 balance_wgs=balance_wgs) as sb:
+                                 balance_wgs=balance_wgs, filters_per_lane=fpl) as sb:
         assert (sb.info.balance_waves > 0) == (balance_wgs > 0)
         xd = torch.from_numpy(x).cuda()
         z, ckpt = sb.forward(xd)
@@ -52,7 +53,7 @@ def test_backward_matches_oracle_gradient(gpu, stride, n, balance_wgs):
         ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
     ea = per_template_rel(ga, ga_ref, bank.offsets)
     eb = per_template_rel(gb, gb_ref, bank.offsets)
-    print(f"stride {stride} n {n}: grad_a rel {ea.max():.2e}, grad_b rel {eb.max():.2e}")
+    print(f"stride {stride} n {n} fpl {fpl}: grad_a rel {ea.max():.2e}, grad_b rel {eb.max():.2e}")
     assert ea.max() <= TOL_GRAD and eb.max() <= TOL_GRAD
 
 

@@ -78,7 +78,7 @@ def test_schedules_on_a_larger_bank(gpu, time_tile, balance_wgs):
 
 
 @pytest.mark.parametrize("time_tile, balance_wgs", [(0, 0), (0, 2), (256, 0)])
-@pytest.mark.parametrize("fpl", [2, 4, 8])
+@pytest.mark.parametrize("fpl", [1, 2, 4, 8])
 def test_filters_per_lane_and_slice_boundaries(gpu, fpl, time_tile, balance_wgs):
     # template sizes around the slot/slice boundaries: 64*fpl filters per slice
     counts = np.array([1, 63, 64, 65, 64 * fpl, 64 * fpl + 1, 3 * 64 * fpl - 7, 0, 2])
