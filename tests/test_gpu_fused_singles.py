@@ -88,9 +88,10 @@ def test_balanced_singles_match_static_schedule_and_peaks(gpu, n, window):
     assert err.max() <= TOL_FP32
 
 
-@pytest.mark.parametrize("fpl, balance_wgs", [(8, 3), (2, 4)])
+@pytest.mark.parametrize("fpl, balance_wgs", [(8, 3), (2, 4), (1, 4)])
 def test_balanced_singles_other_slice_widths(gpu, fpl, balance_wgs):
-    """8 and 2 filters per lane (512 and 128 filters per slice): other single-slice sets."""
+    """8, 2 and 1 filters per lane (512, 128 and 64 filters per slice): other single-slice
+    sets."""
     import torch
     D, n = 3, 512
     bank = mixed_bank(70 + fpl)
@@ -142,9 +143,11 @@ def test_balanced_packets_without_outputs_keep_the_stream(gpu):
 
 @pytest.mark.parametrize("seed, D, fpl, wgs, n, window", [
     (1, 1, 4, 2, 2048, 0), (2, 3, 8, 3, 512, 0), (3, 2, 2, 4, 1000, 0),
-    (4, 1, 4, 1, 2048, 256), (5, 3, 4, 3, 1024, 128), (6, 2, 8, 2, 768, 0)])
+    (4, 1, 4, 1, 2048, 256), (5, 3, 4, 3, 1024, 128), (6, 2, 8, 2, 768, 0),
+    (7, 2, 1, 4, 1024, 256)])
 def test_balanced_equals_static_on_random_banks(gpu, seed, D, fpl, wgs, n, window):
-    """Seeded random banks (empty, one-slice and many-slice templates, delays up to 2047):
+    """Seeded random banks (empty, one-slice and many-slice templates, delays up to 2047; 1-8
+    filters per lane):
     two packets through the balanced schedule give the one-wave-per-slice schedule's z and
     peaks bit for bit."""
     import torch
