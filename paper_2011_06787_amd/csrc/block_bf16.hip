@@ -185,8 +185,8 @@ __device__ __forceinline__ uint32_t lds_byte_addr(uint16_t *smem) {
 // tile blockIdx.x*kStateWaves + w (16 filters) for every detector in turn.  The
 // tile's W' fragments of its first kACache K steps are loaded into registers once and
 // serve every chunk of every detector; further steps (a tile of the precision bank has
-// 11-16 at L = 128) are read again from memory for every chunk.  For every chunk of kChunk blocks the workgroup
-// stages the input range all its tiles read,
+// 11-16 at L = 128) are read again from memory for every chunk.  For every chunk of
+// kChunk blocks the workgroup stages the input range all its tiles read,
 //     x[c0 L + P_lo, (c0 + kChunk - 1) L + P_hi)     (P_lo, P_hi: union band of the tiles)
 // once into LDS (hi and lo planes), skewed by 8 elements per row of L so that the
 // 16-byte fragments of consecutive blocks (columns) start 4 banks apart; the MFMA B
