@@ -399,7 +399,8 @@ __global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_k
     const BTemplate *__restrict__ tmpls, const uint16_t *__restrict__ pa,
     const uint16_t *__restrict__ yt, int64_t y_per_det, const uint16_t *__restrict__ xs,
     int64_t xs_stride, int32_t hist_pad, int32_t n_det, int32_t L, int32_t nb, int32_t n,
-    int32_t n_templates, float *__restrict__ z, int32_t n_col_tiles) {
+    int32_t n_templates, float *__restrict__ z, int32_t n_col_tiles, int32_t ksplit,
+    float *__restrict__ zpart) {
     constexpr int CH = out_col_waves(RW);
     constexpr int kWaves = RW * CH;
     constexpr int kCols = CH * kOutCols;                // columns of the workgroup's tile
@@ -413,8 +414,10 @@ __global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_k
     const int wg = blockIdx.x;
     const int xcd = wg % kXcds;
     const int seq = wg / kXcds;
-    const int t = (seq / n_col_tiles) * kXcds + xcd;
-    const int col_tile = seq % n_col_tiles;
+    const int units = n_col_tiles * ksplit;   // (column tile, K part) pairs per template
+    const int t = (seq / units) * kXcds + xcd;
+    const int col_tile = (seq % units) / ksplit;
+    const int kpart = (seq % units) % ksplit;
     if (t >= n_templates) return;
     const BTemplate bt = tmpls[t];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -424,7 +427,10 @@ __global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_k
     const int kg = (lane / 32) * 8;
     const int ncols = n_det * nb;
     const int64_t row_len = 2 * (int64_t)bt.fpad;
-    const int nks = bt.nks_p + bt.nks_m;
+    // this workgroup's K steps: part kpart of the template's, in order
+    const int nks_all = bt.nks_p + bt.nks_m;
+    const int k_lo = (int)((int64_t)kpart * nks_all / ksplit);
+    const int nks = (int)((int64_t)(kpart + 1) * nks_all / ksplit) - k_lo;
     const uint32_t ring = lds_byte_addr(smem_out);
 
     // global source of the B entries of step ks for column c (8 entries of one plane)
@@ -444,7 +450,8 @@ __global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_k
     // contiguous bytes go to neighbouring lanes, one cache-line request for both
     auto issue = [&](int ks) {
         const int st = (ks % kStages) * kStageElems;
-        const uint16_t *asrc = pa + bt.a_off + (int64_t)ks * rt_per * 1024 + lane * 8;
+        const int kstep = k_lo + ks;   // the template's K step
+        const uint16_t *asrc = pa + bt.a_off + (int64_t)kstep * rt_per * 1024 + lane * 8;
 #pragma unroll
         for (int i = 0; i < kALoadsWg / kWaves; ++i) {
             const int q = wave + i * kWaves;
@@ -455,7 +462,7 @@ __global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_k
             const int q = wave + i * kWaves;
             const int e = q * kWave + lane;
             const int c = (e >> 1) % kCols, plane = (e >> 1) / kCols;
-            lds_dma16(b_src(ks, c, plane, e & 1), smem_out, st + 2 * RW * 1024 + q * kWave * 8);
+            lds_dma16(b_src(kstep, c, plane, e & 1), smem_out, st + 2 * RW * 1024 + q * kWave * 8);
         }
     };
 
@@ -514,7 +521,9 @@ __global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_k
         const int c = col_tile * kCols + ch * kOutCols + ct * 32 + (lane % 32);
         if (c >= ncols) continue;
         const int det = c / nb, blk = c % nb;
-        float *zr = z + 2 * (((int64_t)det * n_templates + t) * n + (int64_t)blk * L);
+        // a split K writes its part's partial sums, added in order by block_ksum_kernel
+        float *zt = ksplit > 1 ? zpart + (int64_t)kpart * 2 * n_det * n_templates * n : z;
+        float *zr = zt + 2 * (((int64_t)det * n_templates + t) * n + (int64_t)blk * L);
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
 #pragma unroll
@@ -529,6 +538,23 @@ __global__ __launch_bounds__(RW * out_col_waves(RW) * kWave) void block_output_k
     }
 }
 
+// z = sum over the K parts of their partial outputs, in part order (deterministic)
+__global__ void block_ksum_kernel(const float4 *__restrict__ zpart, int64_t count, int32_t ksplit,
+                                  float4 *__restrict__ z) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float4 v = zpart[i];
+        for (int p = 1; p < ksplit; ++p) {
+            const float4 w = zpart[(int64_t)p * count + i];
+            v.x += w.x;
+            v.y += w.y;
+            v.z += w.z;
+            v.w += w.w;
+        }
+        z[i] = v;
+    }
+}
+
 }  // namespace
 
 // LDS elements per plane of the staged input of block_state_kernel: the widest union
@@ -537,6 +563,25 @@ int32_t block_state_xwin(const Bank &bk) {
     const int L = bk.block_len;
     const int span = (kChunk - 1) * L + bk.max_wg_band;
     return (int32_t)((span + 8 * (span / L + 1) + 15) / 16 * 16);
+}
+
+// Workgroups sharing one output tile's K steps: when the (template, column tile) pairs of a
+// packet of max_chunk samples are fewer than the compute units, the K steps of each are cut
+// into parts (at least 8 steps each, at most 32 parts) whose partial outputs are summed by a
+// second launch; otherwise 1.
+int32_t block_output_ksplit(const Bank &bk, int32_t min_k_steps) {
+    const int rw = 2 * bk.block_len / 64;
+    const int64_t ncols = (int64_t)bk.n_det * (bk.max_chunk / bk.block_len);
+    const int64_t cols_wg = (int64_t)out_col_waves(rw) * kOutCols;
+    const int64_t wgs = std::max<int64_t>(1, (int64_t)bk.n_templates * ((ncols + cols_wg - 1) / cols_wg));
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    int64_t ks = std::min<int64_t>(cus / wgs, min_k_steps / 8);
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(ks, 32));
 }
 
 // dynamic LDS of block_state_kernel: the staged input and, reusing it, the S rows
@@ -582,14 +627,15 @@ hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *
     }
     const int ncols = bk.n_det * nb;
     const int64_t groups = (bk.n_templates + kXcds - 1) / kXcds;
+    const int32_t ksplit = bk.d_zpart != nullptr ? bk.out_ksplit : 1;
 #define SPIIR_BLOCK_OUT(RW)                                                                   \
     const int col_tiles = (ncols + out_col_waves(RW) * kOutCols - 1) / (out_col_waves(RW) * kOutCols); \
-    const dim3 grid((unsigned)(groups * kXcds * col_tiles));                                  \
+    const dim3 grid((unsigned)(groups * kXcds * col_tiles * ksplit));                         \
     hipLaunchKernelGGL(block_output_kernel<RW>, grid, dim3(RW * out_col_waves(RW) * kWave),      \
                        block_output_lds_bytes(RW), s, bk.d_btmpl,                                \
                        bk.d_pa, bk.d_yt, bk.y_per_det, bk.d_xs, bk.xs_stride, bk.hist_pad,       \
                        bk.n_det, L, nb, n, bk.n_templates, reinterpret_cast<float *>(z),         \
-                       col_tiles)
+                       col_tiles, ksplit, reinterpret_cast<float *>(bk.d_zpart))
     switch (2 * L / 64) {
     case 2: { SPIIR_BLOCK_OUT(2); break; }
     case 4: { SPIIR_BLOCK_OUT(4); break; }
@@ -597,6 +643,13 @@ hipError_t launch_block_bf16(const Bank &bk, const float *x, int32_t n, float2 *
     default: return hipErrorInvalidValue;
     }
 #undef SPIIR_BLOCK_OUT
+    if (ksplit > 1) {
+        const int64_t count = (int64_t)bk.n_det * bk.n_templates * n / 2;   // float4 per part
+        const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+        hipLaunchKernelGGL(block_ksum_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256),
+                           0, s, reinterpret_cast<const float4 *>(bk.d_zpart), count, ksplit,
+                           reinterpret_cast<float4 *>(z));
+    }
     return hipGetLastError();
 }
 

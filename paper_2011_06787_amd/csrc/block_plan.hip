@@ -263,6 +263,10 @@ spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const 
     }
     bk.max_p_blocks = pmax;
     bk.max_m_blocks = mmax;
+    int32_t min_k = INT32_MAX;
+    for (const BTemplate &bt : tm)
+        if (bt.nks_p + bt.nks_m > 0) min_k = std::min(min_k, bt.nks_p + bt.nks_m);
+    bk.out_ksplit = block_output_ksplit(bk, min_k == INT32_MAX ? 0 : min_k);
     if (pmax > 65535 || mmax > 65535) {   // the operand kernels put them on grid.y
         err = "block form: a template's output operand has more than 65535 blocks";
         return SPIIR_E_UNSUPPORTED;
@@ -294,7 +298,10 @@ spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const 
         !alloc((void **)&bk.d_state64, D * (int64_t)ga.size() * sizeof(double2)) ||
         !alloc((void **)&bk.d_yt, 2 * D * bk.y_per_det * 2) ||
         !alloc((void **)&bk.d_xs, 2 * D * bk.xs_stride * 2) ||
-        !alloc((void **)&bk.d_zbuf, D * T * (int64_t)bk.max_chunk * sizeof(float2)))
+        !alloc((void **)&bk.d_zbuf, D * T * (int64_t)bk.max_chunk * sizeof(float2)) ||
+        (bk.out_ksplit > 1 &&
+         !alloc((void **)&bk.d_zpart,
+                (int64_t)bk.out_ksplit * D * T * (int64_t)bk.max_chunk * sizeof(float2))))
         return SPIIR_E_NOMEM;
     struct Up { void *dst; const void *src; size_t bytes; };
     const Up ups[] = {

@@ -155,6 +155,8 @@ struct Bank {
     int64_t block_flop_per_col = 0;   // matrix-core flop of both products per column
     int32_t max_p_blocks = 0;    // output-operand blocks of the largest template: state part
     int32_t max_m_blocks = 0;    // and input part
+    int32_t out_ksplit = 1;      // workgroups sharing one output tile's K steps
+    float2 *d_zpart = nullptr;   // [out_ksplit][D][T][n] partial outputs when out_ksplit > 1
 
     int64_t device_bytes = 0;
     hipStream_t last_stream = nullptr;
@@ -217,6 +219,7 @@ hipError_t launch_trigger_weights(const Bank &bk, float *weight, hipStream_t s);
 hipError_t launch_block_operands(const Bank &bk, hipStream_t s);
 hipError_t launch_block_set_coeffs(const Bank &bk, const float2 *a, const float2 *b, hipStream_t s);
 int32_t block_state_xwin(const Bank &bk);
+int32_t block_output_ksplit(const Bank &bk, int32_t min_k_steps);
 size_t block_state_lds_bytes(const Bank &bk);
 hipError_t prepare_block_bf16(const Bank &bk);
 spiir_status plan_block(Bank &bk, const int32_t *offsets, const float *a, const float *b,
