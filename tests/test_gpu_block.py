@@ -190,3 +190,19 @@ def test_matrix_core_work_reported_per_column(gpu):
         assert sb.info.block_mfma_flop_per_column == (4 + 4 * (2 + 4)) * 32 * 16 * 2 * 3
     with gpu.SpiirBank.from_bank(bank, max_chunk=1024) as sb:
         assert sb.info.block_mfma_flop_per_column == 0
+
+
+@pytest.mark.parametrize("block_len", [64, 128])
+def test_small_bank_split_output_streaming_three_detectors(gpu, block_len):
+    """A bank of 6 templates fills only a few compute units with output tiles, so the output
+    product's K steps are split over workgroups and the parts summed in order: three
+    detectors streamed in three packets match the oracle, and a second identical bank
+    gives the same output bit for bit."""
+    rng = np.random.default_rng(1600 + block_len)
+    bank = synth.draw_filters(rng, np.array([128, 40, 300, 7, 64, 200]))
+    x = rng.standard_normal((3, 3 * 1024)).astype(np.float32)
+    z_ref = oracle.filter(bank, x)
+    z1, _, _, _ = run_block(gpu, bank, x, 1024, block_len=block_len)
+    z2, _, _, _ = run_block(gpu, bank, x, 1024, block_len=block_len)
+    assert np.array_equal(z1, z2)
+    assert oracle.rel_err(z1, z_ref).max() <= TOL_BF16
